@@ -1,0 +1,83 @@
+"""Small hand-built scenes for the pins (no estimator arithmetic here)."""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class V:
+    """A view: view_proj maps world to clip space."""
+    width: int
+    height: int
+    view_proj: np.ndarray
+    cam_pos: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
+    near: float = 0.1
+
+
+def ndc_view(w, h):
+    """Identity projection: world x, y, z are NDC and clip w = 1."""
+    return V(w, h, np.eye(4, dtype=np.float32), np.array([0, 0, 3], np.float32))
+
+
+@dataclass
+class SimpleScene:
+    tri: np.ndarray
+    corner_uv: np.ndarray
+    pos: np.ndarray
+    tex: list
+    shading: int = 0
+    tex_mode: int = 0
+    light_dir: np.ndarray = field(default_factory=lambda: np.array([0, 0, 1], np.float32))
+    light_rgb: np.ndarray = field(default_factory=lambda: np.ones(3, np.float32))
+    ambient: float = 0.1
+    diffuse: float = 0.9
+
+    @property
+    def n_verts(self):
+        return self.pos.shape[0]
+
+    def flat(self, pos=None, tex=None):
+        pos = self.pos if pos is None else pos
+        tex = self.tex if tex is None else tex
+        return np.concatenate([np.asarray(pos, np.float32).reshape(-1)]
+                              + [np.asarray(t, np.float32).reshape(-1) for t in tex])
+
+
+def quad_scene(tex, z=0.0, extent=1.0, uv_scale=1.0, shading=0):
+    """Two triangles covering [-extent, extent]^2 at depth z, UV = [0,1]^2
+    (u right, v down on screen)."""
+    e = extent
+    pos = np.array([(-e, e, z), (e, e, z), (e, -e, z), (-e, -e, z)], np.float32)
+    tri = np.array([(0, 3, 1), (1, 3, 2)], np.int32)
+    uvv = np.array([(0, 0), (1, 0), (1, 1), (0, 1)], np.float32) * uv_scale
+    corner_uv = uvv[tri].astype(np.float32)
+    return SimpleScene(tri, corner_uv, pos, [np.asarray(tex, np.float32)], shading=shading)
+
+
+def grid_scene(n, jitter, seed, z=0.0, lo=-0.9, hi=0.9, tex=None):
+    """A planar n x n grid of quads over [lo, hi]^2 split into triangles,
+    interior vertices jittered; a watertight tessellation of the square."""
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(lo, hi, n + 1)
+    P = np.array([(x, y, z) for y in xs for x in xs], np.float64)
+    step = (hi - lo) / n
+    for j in range(1, n):
+        for i in range(1, n):
+            k = j * (n + 1) + i
+            P[k, :2] += rng.uniform(-jitter, jitter, 2) * step
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a = j * (n + 1) + i
+            b, c, d = a + 1, a + n + 1, a + n + 2
+            if (i + j) % 2:
+                tris += [(a, b, d), (a, d, c)]
+            else:
+                tris += [(a, b, c), (b, d, c)]
+    tri = np.array(tris, np.int32)
+    corner_uv = np.zeros((len(tri), 3, 2), np.float32)
+    if tex is None:
+        tex = np.full((4, 4, 3), 0.5, np.float32)
+    return SimpleScene(tri, corner_uv, P.astype(np.float32), [tex])

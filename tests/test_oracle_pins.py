@@ -1,0 +1,602 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks one part of the oracle against a library routine, a closed
+form, an invariant of the mathematics or a brute-force evaluation, so that a
+plausible mistake (a dropped term, a wrong sign or index, a transposed
+operand) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as Fn
+
+import oracle
+from paper_2404_09758_amd import scenes as S
+from tests import helpers as H
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox ---
+
+@pytest.mark.parametrize("ctr,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([5, 3, 7, 11], [123456789, 0]),
+    ([2**64 - 1, 2**64 - 1, 2**64 - 1, 2**64 - 1], [2**64 - 1, 2**64 - 1]),
+    ([0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0, 0x082EFA98EC4E6C89],
+     [0x452821E638D01377, 0xBE5466CF34E90C6C]),
+])
+def test_philox_matches_numpy(ctr, key, oracle_lib):
+    """numpy's Philox bit generator is Philox4x64-10; it increments its
+    counter before each block, so counter c-1 yields block c."""
+    c = np.array(ctr, np.uint64)
+    prev = c.copy()
+    # c - 1 with borrow across the four words
+    for w in range(4):
+        if prev[w] != 0:
+            prev[w] -= np.uint64(1)
+            break
+        prev[w] = np.uint64(2**64 - 1)
+    bg = np.random.Philox(key=np.array(key, np.uint64), counter=prev)
+    ref = bg.random_raw(4).astype(np.uint64)
+    got = oracle.philox4x64_10(c, np.array(key, np.uint64))
+    assert np.array_equal(got, ref)
+
+
+def test_sign_bits_follow_philox_words(oracle_lib):
+    seed, step, pair, scene = 0xDEADBEEF1234, 7, 3, 2
+    d = 1000
+    s = oracle.signs(seed, step, pair, scene, d)
+    for base in range(0, d, 256):
+        r = oracle.philox4x64_10(np.array([base >> 8, pair, step, scene], np.uint64),
+                                 np.array([seed, 0], np.uint64))
+        for j in range(min(256, d - base)):
+            bit = (int(r[j >> 6]) >> (j & 63)) & 1
+            assert s[base + j] == (-1 if bit else 1)
+
+
+def test_sign_balance_and_independence(oracle_lib):
+    """Each sign is +-1 with probability 1/2 (Sec. 3, Eq. 4): mean and lag-1
+    correlation within 5 sigma over 2^21 draws."""
+    d = 1 << 21
+    s = oracle.signs(42, 1, 0, 0, d).astype(np.float64)
+    assert set(np.unique(s)) == {-1.0, 1.0}
+    sigma = 1.0 / math.sqrt(d)
+    assert abs(s.mean()) < 5 * sigma
+    assert abs((s[1:] * s[:-1]).mean()) < 5 * sigma
+    # different pairs give (nearly) uncorrelated vectors
+    s2 = oracle.signs(42, 1, 1, 0, d).astype(np.float64)
+    assert abs((s * s2).mean()) < 5 * sigma
+
+
+# ------------------------------------------------------------- quantiser ---
+
+def test_quantizer_round_half_even_and_saturation(oracle_lib):
+    q = oracle.quantize
+    assert q(0.0) == 0
+    assert q(2.0 ** -33) == 0                    # 0.5 -> 0
+    assert q(3 * 2.0 ** -33) == 2                # 1.5 -> 2
+    assert q(5 * 2.0 ** -33) == 2                # 2.5 -> 2
+    assert q(-3 * 2.0 ** -33) == -2
+    assert q(1.0) == 2 ** 32
+    assert q(-0.75) == -3 * 2 ** 30
+    assert q(32.0) == 2 ** 37
+    assert q(33.0) == 2 ** 37
+    assert q(-1e30) == -(2 ** 37)
+    assert q(float("inf")) == 2 ** 37
+    assert q(float("nan")) == 0
+    rng = np.random.default_rng(0)
+    for x in rng.normal(0, 1, 200).astype(np.float32):
+        assert q(x) == -q(-x)
+        assert q(x) == int(np.rint(np.float64(x) * 2.0 ** 32))
+
+
+# ---------------------------------------------------------------- layout ---
+
+def test_param_count_matches_paper_table(oracle_lib):
+    """d = 3 V + 3 texels reproduces the two parameter counts the paper
+    prints (performance comparison table, Sec. 6.2)."""
+    g = json.load(open(os.path.join(GOLDEN, "param_counts.json")))
+    for row in g["mesh_texture"]:
+        sc = H.SimpleScene(np.zeros((1, 3), np.int32), np.zeros((1, 3, 2), np.float32),
+                           np.zeros((row["vertices"], 3), np.float32), [])
+        o = oracle.Oracle(sc, tex_shapes=[tuple(row["texture"])])
+        assert o.d == row["d"]
+        assert S.param_count(row["vertices"], [tuple(row["texture"])]) == row["d"]
+
+
+# ---------------------------------------------------------------- raster ---
+
+def _single_tri_masks(sc, view):
+    masks = []
+    for t in range(len(sc.tri)):
+        one = H.SimpleScene(sc.tri[t:t + 1], sc.corner_uv[t:t + 1], sc.pos, sc.tex)
+        o = oracle.Oracle(one)
+        _, ids, _ = o.render(one.flat(), view)
+        masks.append(ids != oracle.BG_ID)
+    return np.array(masks)
+
+
+def test_fullscreen_quad_covers_every_pixel_once(oracle_lib):
+    sc = H.quad_scene(np.full((4, 4, 3), 0.5), extent=1.3)
+    view = H.ndc_view(24, 17)
+    masks = _single_tri_masks(sc, view)
+    assert np.all(masks.sum(0) == 1)
+    o = oracle.Oracle(sc)
+    _, ids, _ = o.render(sc.flat(), view)
+    assert set(np.unique(ids)) == {0, 1}
+
+
+@pytest.mark.parametrize("jitter,seed", [(0.0, 0), (0.35, 1), (0.45, 2)])
+def test_tessellation_is_watertight(jitter, seed, oracle_lib):
+    """A planar tessellation covers each pixel centre inside it exactly once
+    (top-left rule), including centres lying exactly on shared edges."""
+    W = 32
+    n = 4
+    # unjittered vertices sit on pixel centres 3.5, 9.5, ..., 27.5 (6 px apart)
+    lo, hi = 2 * 3.5 / W - 1, 2 * 27.5 / W - 1
+    sc = H.grid_scene(n, jitter, seed, lo=lo, hi=hi)
+    view = H.ndc_view(W, W)
+    masks = _single_tri_masks(sc, view)
+    cover = masks.sum(0)
+    assert cover.max() == 1
+    assert np.all(cover[4:27, 4:27] == 1)
+    assert cover[:3].sum() == 0 and cover[29:].sum() == 0
+    if jitter == 0.0:
+        sx = (np.linspace(lo, hi, n + 1) + 1) * W / 2
+        assert np.allclose(sx - 0.5, np.round(sx - 0.5))
+
+
+def test_depth_then_lower_id_wins(oracle_lib):
+    tex = np.full((2, 2, 3), 0.5)
+    big = np.array([(-0.8, 0.8, 0.2), (0.8, 0.8, 0.2), (0.0, -0.8, 0.2)], np.float32)
+    near = big.copy()
+    near[:, 2] = -0.3
+    # duplicates: identical triangles, ids 0 and 1 -> 0 wins everywhere
+    pos = np.concatenate([big, big])
+    sc = H.SimpleScene(np.array([(0, 1, 2), (3, 4, 5)], np.int32), np.zeros((2, 3, 2), np.float32), pos, [tex])
+    _, ids, _ = oracle.Oracle(sc).render(sc.flat(), H.ndc_view(20, 20))
+    assert set(np.unique(ids)) == {0, oracle.BG_ID}
+    # nearer triangle listed second still wins (depth decides first)
+    pos = np.concatenate([big, near])
+    sc = H.SimpleScene(np.array([(0, 1, 2), (3, 5, 4)], np.int32), np.zeros((2, 3, 2), np.float32), pos, [tex])
+    _, ids, _ = oracle.Oracle(sc).render(sc.flat(), H.ndc_view(20, 20))
+    assert set(np.unique(ids)) == {1, oracle.BG_ID}
+
+
+def test_raster_matches_float64_point_in_triangle(oracle_lib):
+    """Random layered triangles: ids equal a float64 brute force (nearest
+    layer containing the pixel centre) away from edges (> 1/64 px)."""
+    rng = np.random.default_rng(7)
+    W, Hh = 48, 40
+    n = 30
+    pos = rng.uniform(-1.1, 1.1, (3 * n, 3)).astype(np.float32)
+    depth = rng.permutation(n) / n * 1.6 - 0.8
+    pos[:, 2] = np.repeat(depth, 3)
+    tri = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    sc = H.SimpleScene(tri, np.zeros((n, 3, 2), np.float32), pos, [np.full((2, 2, 3), 0.5)])
+    _, ids, _ = oracle.Oracle(sc).render(sc.flat(), H.ndc_view(W, Hh))
+    sx = (pos[:, 0].astype(np.float64) * 0.5 + 0.5) * W
+    sy = (0.5 - pos[:, 1].astype(np.float64) * 0.5) * Hh
+    px, py = np.meshgrid(np.arange(W) + 0.5, np.arange(Hh) + 0.5)
+    best = np.full((Hh, W), np.inf)
+    ref = np.full((Hh, W), oracle.BG_ID, np.int64)
+    ambiguous = np.zeros((Hh, W), bool)
+    for t in range(n):
+        a, b, c = 3 * t, 3 * t + 1, 3 * t + 2
+        X = [sx[a], sx[b], sx[c]]
+        Y = [sy[a], sy[b], sy[c]]
+        area = (X[1] - X[0]) * (Y[2] - Y[0]) - (Y[1] - Y[0]) * (X[2] - X[0])
+        if abs(area) < 1e-9:
+            continue
+        inside = np.ones((Hh, W), bool)
+        near_edge = np.zeros((Hh, W), bool)
+        for k in range(3):
+            i, j = (k + 1) % 3, (k + 2) % 3
+            e = ((X[j] - X[i]) * (py - Y[i]) - (Y[j] - Y[i]) * (px - X[i])) * np.sign(area)
+            length = math.hypot(X[j] - X[i], Y[j] - Y[i])
+            inside &= e > 0
+            near_edge |= np.abs(e) / length < 1.0 / 64
+        ambiguous |= near_edge
+        z = depth[t]
+        upd = inside & (z < best)
+        best[upd] = z
+        ref[upd] = t
+    ok = ~ambiguous
+    assert ok.mean() > 0.7
+    assert np.array_equal(ids.astype(np.int64)[ok], ref[ok])
+
+
+# ---------------------------------------------- attributes and sampling ---
+
+def _wrap_pad(tex):
+    """Texture padded so that grid_sample(border) reproduces u-wrap and v-clamp."""
+    t = torch.as_tensor(np.asarray(tex, np.float32)).permute(2, 0, 1)
+    t = torch.cat([t[:, :, -1:], t, t[:, :, :1]], dim=2)
+    t = torch.cat([t[:, :1, :], t, t[:, -1:, :]], dim=1)
+    return t[None]
+
+
+def _grid_sample_wrap(tex_t, u, v, Wt, Ht):
+    """tex_t: padded [1,C,Ht+2,Wt+2] tensor; u, v: float64 arrays."""
+    u = np.mod(u, 1.0)
+    gx = (u * Wt + 1.0) / (Wt + 2) * 2.0 - 1.0
+    gy = (v * Ht + 1.0) / (Ht + 2) * 2.0 - 1.0
+    grid = torch.as_tensor(np.stack([gx, gy], -1)[None, None], dtype=torch.float32)
+    out = Fn.grid_sample(tex_t, grid, mode="bilinear", padding_mode="border", align_corners=False)
+    return out[0, :, 0, :].T        # [n, C]
+
+
+def test_bilinear_matches_grid_sample(oracle_lib):
+    rng = np.random.default_rng(3)
+    tex = rng.random((5, 7, 3)).astype(np.float32)
+    sc = H.quad_scene(tex, extent=1.0, uv_scale=1.0)
+    _ = sc
+    # a slanted uv mapping that crosses the u seam and the v borders
+    sc.corner_uv = (sc.corner_uv * np.array([1.7, 1.2], np.float32) - np.array([0.4, 0.1], np.float32))
+    view = H.ndc_view(37, 29)
+    rgb, ids, uv = oracle.Oracle(sc).render(sc.flat(), view)
+    m = ids != oracle.BG_ID
+    ref = _grid_sample_wrap(_wrap_pad(tex), uv[m][:, 0].astype(np.float64), uv[m][:, 1].astype(np.float64),
+                            7, 5).numpy()
+    assert np.abs(rgb[m] - ref).max() < 2e-6
+
+
+def test_perspective_correct_uv_matches_ray_plane(oracle_lib):
+    """UVs equal the texture coordinates of the ray-plane hit point of each
+    pixel centre on a slanted quad (perspective-correct interpolation)."""
+    ang = math.radians(55.0)
+    R = np.array([[math.cos(ang), 0, math.sin(ang)], [0, 1, 0], [-math.sin(ang), 0, math.cos(ang)]])
+    local = np.array([(-1, 1, 0), (1, 1, 0), (1, -1, 0), (-1, -1, 0)], np.float64)
+    pos = (local @ R.T).astype(np.float32)
+    tri = np.array([(0, 3, 1), (1, 3, 2)], np.int32)
+    uvv = np.array([(0, 0), (1, 0), (1, 1), (0, 1)], np.float32)
+    sc = H.SimpleScene(tri, uvv[tri], pos, [np.full((2, 2, 3), 0.5, np.float32)])
+    view = S.look_at_view(64, 48, 0.0, 0.0)
+    _, ids, uv = oracle.Oracle(sc).render(sc.flat(), view)
+    m = ids != oracle.BG_ID
+    assert m.sum() > 500
+    inv = np.linalg.inv(view.view_proj.astype(np.float64))
+    ys, xs = np.nonzero(m)
+    nx = (xs + 0.5) / 64 * 2 - 1
+    ny = 1 - (ys + 0.5) / 48 * 2
+    p0 = np.stack([nx, ny, -np.ones_like(nx), np.ones_like(nx)], 1) @ inv.T
+    p1 = np.stack([nx, ny, np.ones_like(nx), np.ones_like(nx)], 1) @ inv.T
+    p0 = p0[:, :3] / p0[:, 3:]
+    p1 = p1[:, :3] / p1[:, 3:]
+    nrm = R @ np.array([0, 0, 1.0])
+    t = -(p0 @ nrm) / ((p1 - p0) @ nrm)
+    hit = p0 + t[:, None] * (p1 - p0)
+    loc = hit @ R                     # back to the quad's local frame
+    ref_u = (loc[:, 0] + 1) / 2
+    ref_v = (1 - loc[:, 1]) / 2
+    err = np.maximum(np.abs(uv[m][:, 0] - ref_u), np.abs(uv[m][:, 1] - ref_v))
+    assert err.max() < 2e-3
+    # an affine (screen-space) interpolation would be far off on this slant
+    assert np.abs(ref_u - (xs + 0.5 - xs.min()) / (xs.max() - xs.min() + 1)).max() > 0.02
+
+
+# --------------------------------------------------------------- shading ---
+
+def _facing_triangle(width=15):
+    pos = np.array([(-2, -2, 0), (2, -2, 0), (0, 2, 0)], np.float32)
+    tri = np.array([(0, 1, 2)], np.int32)
+    # u increases along +x, v along -y
+    uv = np.array([[(0.0, 1.0), (1.0, 1.0), (0.5, 0.0)]], np.float32)
+    return pos, tri, uv, S.look_at_view(width, width, 0.0, 0.0)
+
+
+def test_lambert_closed_form(oracle_lib):
+    ang = math.radians(35.0)
+    pos, tri, uv, view = _facing_triangle()
+    albedo = np.array([0.6, 0.4, 0.2], np.float32)
+    sc = H.SimpleScene(tri, uv, pos, [np.tile(albedo, (3, 3, 1))], shading=S.SHADING_LAMBERT,
+                       light_dir=np.array([math.sin(ang), 0, math.cos(ang)], np.float32),
+                       light_rgb=np.array([1.0, 2.0, 0.5], np.float32), ambient=0.1, diffuse=0.9)
+    rgb, ids, _ = oracle.Oracle(sc).render(sc.flat(), view)
+    ref = albedo * (0.1 + 0.9 * math.cos(ang)) * np.array([1.0, 2.0, 0.5])
+    assert np.abs(rgb[ids != oracle.BG_ID] - ref).max() < 1e-6
+
+
+def _ggx_ref(alb, rough, ndl, ndv, ndh, vdh, E, amb):
+    """Textbook Cook-Torrance: GGX/Trowbridge-Reitz D, Smith-Schlick G with
+    k = alpha/2, Schlick Fresnel with F0 = 0.04, alpha = roughness^2."""
+    a = max(rough * rough, 0.002)
+    a2 = a * a
+    D = a2 / (math.pi * (ndh * ndh * (a2 - 1) + 1) ** 2)
+    k = a / 2
+    G = (ndl / (ndl * (1 - k) + k)) * (ndv / (ndv * (1 - k) + k))
+    F = 0.04 + 0.96 * (1 - vdh) ** 5
+    spec = D * G * F / (4 * ndl * ndv)
+    return (alb / math.pi + spec) * E * ndl + amb * alb
+
+
+@pytest.mark.parametrize("rough,light_deg,tilt_deg", [(1.0, 0.0, 0.0), (0.5, 0.0, 0.0),
+                                                      (0.6, 60.0, 0.0), (0.8, 0.0, 30.0),
+                                                      (0.4, 40.0, -25.0)])
+def test_ggx_closed_form_at_centre_pixel(rough, light_deg, tilt_deg, oracle_lib):
+    """At the centre pixel the view ray hits the origin, so v = +z exactly;
+    the normal map tilts n towards +u (= +x) by tilt_deg."""
+    pos, tri, uv, view = _facing_triangle()
+    albedo = np.array([0.6, 0.4, 0.2], np.float32)
+    la = math.radians(light_deg)
+    L = np.array([math.sin(la), 0.0, math.cos(la)])
+    ta = math.radians(tilt_deg)
+    nmv = np.array([0.5 + 0.5 * math.sin(ta), 0.5, 0.5 + 0.5 * math.cos(ta)], np.float32)
+    tex = [np.tile(albedo, (4, 4, 1)), np.tile(nmv, (4, 4, 1)), np.full((4, 4, 1), rough, np.float32)]
+    sc = H.SimpleScene(tri, uv, pos, tex, shading=S.SHADING_GGX, light_dir=L.astype(np.float32),
+                       light_rgb=np.array([1.0, 1.0, 1.0], np.float32), ambient=0.03)
+    rgb, ids, _ = oracle.Oracle(sc).render(sc.flat(), view)
+    assert ids[7, 7] == 0
+    nm = np.array([2 * float(nmv[0]) - 1, 2 * float(nmv[1]) - 1, 2 * float(nmv[2]) - 1])
+    n = nm / np.linalg.norm(nm)              # T = +x, B = +y, N = +z
+    v = np.array([0, 0, 1.0])
+    h = (L + v) / np.linalg.norm(L + v)
+    ref = [_ggx_ref(float(a), rough, max(n @ L, 0), max(n @ v, 0), max(n @ h, 0), max(v @ h, 0), 1.0, 0.03)
+           for a in albedo]
+    assert np.allclose(rgb[7, 7], ref, rtol=2e-5, atol=1e-6)
+
+
+# -------------------------------------------------- estimator: closed form ---
+
+def _torch_grad_of_l2(tex, uv, mask, target):
+    """d/d tex of sum_p || bilinear(tex, uv_p) - target_p ||^2 by autograd."""
+    Ht, Wt, _ = tex.shape
+    t = torch.tensor(np.asarray(tex, np.float32), requires_grad=True)
+    tt = t.permute(2, 0, 1)
+    tt = torch.cat([tt[:, :, -1:], tt, tt[:, :, :1]], dim=2)
+    tt = torch.cat([tt[:, :1, :], tt, tt[:, -1:, :]], dim=1)[None]
+    c = _grid_sample_wrap(tt, uv[mask][:, 0].astype(np.float64), uv[mask][:, 1].astype(np.float64), Wt, Ht)
+    f = ((c - torch.as_tensor(target[mask])) ** 2).sum()
+    f.backward()
+    return t.grad.numpy().reshape(-1).astype(np.float64)
+
+
+def test_T1_onehot_texel_recovers_analytic_gradient(oracle_lib):
+    """Unlit, bilinear, L2, one texel perturbed by +-delta: the antithetic
+    difference of a quadratic is exact, so Q_j 2^-32 / (2 delta) equals
+    d f / d theta_j (Eq. 8 with a single non-zero sign)."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    rgb, ids, uv = o.render(theta, sc.views[0])
+    mask = ids != oracle.BG_ID
+    g_ref = _torch_grad_of_l2(sc.tex[0], uv, mask, tgt)
+    delta = 1e-2
+    eps = [0.0, delta]
+    base = 3 * sc.n_verts
+    hit = np.nonzero(np.abs(g_ref) > 1e-3)[0]
+    rng = np.random.default_rng(0)
+    for j in rng.choice(hit, 12, replace=False):
+        s = np.zeros((1, o.d), np.int8)
+        s[0, base + j] = 1 if j % 2 else -1
+        Q, K, G64, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, eps, signs_=s, want_g64=True)
+        est = Q[base + j] * 2.0 ** -32 / (2 * delta)
+        # f+- are fp32 sums of O(1) squares: each pixel's difference carries up
+        # to ~2 ulp(1) = 2.4e-7 of rounding, i.e. 1.2e-5 after / (2 delta)
+        n_pix = int(K[sc.n_verts + j // 3])
+        tol = n_pix * 1.2e-5
+        assert est == pytest.approx(g_ref[j], rel=1e-4, abs=tol)
+        assert G64[base + j] == pytest.approx(g_ref[j], rel=1e-4, abs=tol)
+        assert np.count_nonzero(Q) == 1
+
+
+# ------------------------------------------- estimator: Eq. 3 brute force ---
+
+@pytest.mark.parametrize("shading", [S.SHADING_UNLIT, S.SHADING_LAMBERT, S.SHADING_GGX])
+def test_T2_onehot_equals_full_image_finite_difference(shading, oracle_lib):
+    """With s = e_i, the per-pixel estimator (sum over the pixels whose
+    contribution set holds theta_i) equals the quantised central difference
+    of Eq. 3 summed over ALL pixels, bit for bit: every pixel whose colour
+    depends on theta_i is in the set (union of the two renders)."""
+    sc = S.make_tiny()
+    nt = 3 if shading == S.SHADING_GGX else 1
+    tex = sc.tex[:1]
+    ttex = sc.target_tex[:1]
+    if nt == 3:
+        rng = np.random.default_rng(5)
+        tex = tex + [rng.random((64, 64, 3)).astype(np.float32), rng.uniform(0.2, 0.9, (32, 32, 1)).astype(np.float32)]
+        ttex = ttex + [np.full((64, 64, 3), 0.5, np.float32), np.full((32, 32, 1), 0.5, np.float32)]
+    sc2 = H.SimpleScene(sc.tri, sc.corner_uv, sc.pos, tex, shading=shading,
+                        light_dir=S.unit_light(), ambient=0.1)
+    o = oracle.Oracle(sc2)
+    theta = sc2.flat()
+    tgt, _, _ = o.render(sc2.flat(sc.target_pos, ttex), sc.views[0])
+    eps = [3e-3, 1e-2, 1e-2, 1e-2][: 1 + nt]
+    _, ids, _ = o.render(theta, sc.views[0])
+    visible = np.unique(ids[ids != oracle.BG_ID])
+    vis_verts = np.unique(sc.tri[visible].reshape(-1))
+    rng = np.random.default_rng(11)
+    params = list(3 * rng.choice(vis_verts, 6, replace=False) + rng.integers(0, 3, 6))
+    params += list(3 * sc.n_verts + rng.choice(64 * 64 * 3, 6, replace=False))
+    if nt == 3:
+        params += list(3 * sc.n_verts + 2 * 64 * 64 * 3 + rng.choice(32 * 32, 3, replace=False))
+    nonzero = 0
+    for i in params:
+        s = np.zeros((1, o.d), np.int8)
+        s[0, i] = -1 if i % 3 == 0 else 1
+        Q, K, _, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, eps, signs_=s)
+        fp = o.pixel_loss(theta, sc.views[0], tgt, signs_=s[0], sign=+1, eps=eps)
+        fm = o.pixel_loss(theta, sc.views[0], tgt, signs_=s[0], sign=-1, eps=eps)
+        brute = sum(oracle.quantize(x) for x in (fp - fm).reshape(-1))
+        assert Q[i] == int(s[0, i]) * brute
+        nonzero += brute != 0
+    assert nonzero >= len(params) // 2
+
+
+# ------------------------------------------ estimator: exact expectation ---
+
+def test_T3_exhaustive_sign_average_is_gradient(oracle_lib):
+    """Over all 2^12 sign vectors of a 2x2 RGB texture, the mean of Eq. 8
+    equals the gradient exactly (E[s_i s_j] = delta_ij; f is quadratic in
+    the texels for an unlit bilinear render)."""
+    rng = np.random.default_rng(9)
+    tex = rng.random((2, 2, 3)).astype(np.float32)
+    sc = H.quad_scene(tex, extent=1.0)
+    view = H.ndc_view(16, 16)
+    o = oracle.Oracle(sc)
+    theta = sc.flat()
+    tgt = rng.random((16, 16, 3)).astype(np.float32)
+    k = 12
+    base = 12
+    combos = ((np.arange(2 ** k)[:, None] >> np.arange(k)[None, :]) & 1).astype(np.int8)
+    signs = np.ones((2 ** k, o.d), np.int8)
+    signs[:, base:] = 1 - 2 * combos
+    eps = [0.0, 1e-2]
+    Q, K, G64, _ = o.estimate(theta, [view], [tgt], 0, 1, 2 ** k, eps, signs_=signs, want_g64=True)
+    mean = G64[base:] / 2 ** k
+    _, ids, uv = o.render(theta, view)
+    g_ref = _torch_grad_of_l2(tex, uv, ids != oracle.BG_ID, tgt)
+    assert np.allclose(mean, g_ref, rtol=1e-4, atol=1e-5)
+    # the fixed-point sums agree with the unquantised ones
+    assert np.allclose(Q[base:] * 2.0 ** -32 / (2 * 1e-2) / 2 ** k, mean, rtol=1e-5, atol=1e-6)
+
+
+def test_T4_antithetic_symmetry_bit_exact(oracle_lib):
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    s = oracle.signs(99, 3, 0, 0, o.d)[None]
+    Qa, Ka, _, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, sc.eps, signs_=s)
+    Qb, Kb, _, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, sc.eps, signs_=-s)
+    assert np.array_equal(Qa, Qb) and np.array_equal(Ka, Kb)
+    # and Philox signs are what the table path uses
+    Qc, Kc, _, _ = o.estimate(theta, sc.views, [tgt], 99, 3, 1, sc.eps)
+    assert np.array_equal(Qa, Qc) and np.array_equal(Ka, Kc)
+
+
+# ---------------------------------------------------------- bookkeeping ---
+
+def test_T7_counts_are_union_of_vertex_sets(oracle_lib):
+    """Positions only: sum_g K_g equals sum_p |verts(ID+) U verts(ID-)|."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    eps = [5e-3, 0.0]
+    s = oracle.signs(5, 1, 0, 0, o.d)
+    Q, K, _, _ = o.estimate(theta, sc.views, [tgt], 5, 1, 1, eps)
+    _, idp, _ = o.render(theta, sc.views[0], signs_=s, sign=+1, eps=eps)
+    _, idm, _ = o.render(theta, sc.views[0], signs_=s, sign=-1, eps=eps)
+    total = 0
+    per_vertex = np.zeros(sc.n_verts, np.int64)
+    for a, b in zip(idp.reshape(-1), idm.reshape(-1)):
+        vs = set()
+        if a != oracle.BG_ID:
+            vs |= set(sc.tri[a].tolist())
+        if b != oracle.BG_ID:
+            vs |= set(sc.tri[b].tolist())
+        total += len(vs)
+        for v in vs:
+            per_vertex[v] += 1
+    assert int(K.sum()) == total
+    assert np.array_equal(K[: sc.n_verts].astype(np.int64), per_vertex)
+    assert np.all(K[sc.n_verts:] == 0)                  # texels frozen
+    assert np.all(Q[3 * sc.n_verts:] == 0)
+    assert (idp != idm).sum() > 0                       # union case exercised
+
+
+def test_nearest_mode_counts_nearest_texels(oracle_lib):
+    sc = S.make_tiny()
+    sc.tex_mode = S.TEX_NEAREST
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    eps = [0.0, 1e-2]
+    Q, K, _, _ = o.estimate(theta, sc.views, [tgt], 5, 1, 1, eps)
+    _, ids, uv = o.render(theta, sc.views[0])
+    m = ids != oracle.BG_ID
+    u = uv[m][:, 0].astype(np.float32)
+    v = uv[m][:, 1].astype(np.float32)
+    x = u * np.float32(64) - np.float32(0.5)
+    y = v * np.float32(64) - np.float32(0.5)
+    xn = np.floor(x).astype(np.int64) + (x - np.floor(x) >= 0.5)
+    yn = np.clip(np.floor(y).astype(np.int64) + (y - np.floor(y) >= 0.5), 0, 63)
+    cnt = np.bincount(yn * 64 + np.mod(xn, 64), minlength=64 * 64)
+    assert np.array_equal(K[sc.n_verts:].astype(np.int64), cnt)
+
+
+# ------------------------------------------------------------- optimiser ---
+
+def test_adam_matches_torch(oracle_lib):
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    rng = np.random.default_rng(1)
+    theta = sc.flat_params().copy()
+    m = np.zeros(o.d, np.float32)
+    v = np.zeros(o.d, np.float32)
+    eps = [1e-3, 1e-2]
+    lr = [2e-3, 3e-2]
+    p_pos = torch.tensor(theta[: 3 * sc.n_verts].astype(np.float64), requires_grad=True)
+    p_tex = torch.tensor(theta[3 * sc.n_verts:].astype(np.float64), requires_grad=True)
+    opt = torch.optim.Adam([{"params": [p_pos], "lr": lr[0]}, {"params": [p_tex], "lr": lr[1]}],
+                           betas=(0.9, 0.999), eps=1e-8)
+    for t in range(1, 5):
+        Q = rng.integers(-2 ** 40, 2 ** 40, o.d).astype(np.int64)
+        K = rng.integers(1, 9, o.G).astype(np.uint32)
+        g = o.decode(Q, K, eps, S.AVG_COUNT, 1)
+        o.step(theta, m, v, t, Q, K, eps, 1, kind=S.OPT_ADAM, averaging=S.AVG_COUNT, lr=lr)
+        assert not Q.any() and not K.any()
+        opt.zero_grad()
+        p_pos.grad = torch.tensor(g[: 3 * sc.n_verts].astype(np.float64))
+        p_tex.grad = torch.tensor(g[3 * sc.n_verts:].astype(np.float64))
+        opt.step()
+        ref = np.concatenate([p_pos.detach().numpy(), p_tex.detach().numpy()])
+        assert np.allclose(theta, ref, rtol=1e-6, atol=2e-7)
+
+
+def test_decode_averaging_and_skip_rules(oracle_lib):
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    Q = np.zeros(o.d, np.int64)
+    K = np.zeros(o.G, np.uint32)
+    Q[0] = 3 * 2 ** 32          # vertex 0, x
+    K[0] = 4
+    Q[5] = 2 ** 32              # vertex 1, z; K[1] = 0
+    eps = [0.5, 1e-2]
+    g = o.decode(Q, K, eps, S.AVG_COUNT, 7)
+    assert g[0] == pytest.approx(3.0 / (2 * 0.5 * 4))
+    assert g[5] == 0.0
+    g = o.decode(Q, K, eps, S.AVG_PAIRS, 7)
+    assert g[0] == pytest.approx(3.0 / (2 * 0.5 * 7))
+    assert g[5] == pytest.approx(1.0 / (2 * 0.5 * 7))
+    # count mode: a group with K = 0 is not updated at all
+    theta = np.ones(o.d, np.float32)
+    m = np.zeros(o.d, np.float32)
+    v = np.zeros(o.d, np.float32)
+    Q2, K2 = Q.copy(), K.copy()
+    o.step(theta, m, v, 1, Q2, K2, eps, 7, kind=S.OPT_SGD, averaging=S.AVG_COUNT, lr=[0.1, 0.1])
+    assert theta[0] == np.float32(1.0) - np.float32(0.1) * np.float32(0.75)
+    assert theta[5] == 1.0 and theta[3] == 1.0
+    # frozen block: no update even with counts
+    theta = np.ones(o.d, np.float32)
+    Q2, K2 = Q.copy(), K.copy()
+    o.step(theta, m, v, 1, Q2, K2, [0.0, 1e-2], 7, kind=S.OPT_SGD, averaging=S.AVG_PAIRS, lr=[0.1, 0.1])
+    assert np.all(theta == 1.0)
+
+
+def test_T9_tiny_sgd_lowers_loss(oracle_lib):
+    """50 SGD steps on the tiny configuration lower the L2 image error (a
+    convergence smoke test, not a parity pin)."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params().copy()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    m = np.zeros(o.d, np.float32)
+    v = np.zeros(o.d, np.float32)
+
+    def loss(th):
+        return float(o.pixel_loss(th, sc.views[0], tgt).astype(np.float64).sum())
+
+    l0 = loss(theta)
+    for t in range(1, 51):
+        Q, K, _, _ = o.estimate(theta, sc.views, [tgt], 1234, t, 1, sc.eps)
+        o.step(theta, m, v, t, Q, K, sc.eps, 1, kind=S.OPT_SGD, averaging=S.AVG_COUNT, lr=sc.lr)
+    l1 = loss(theta)
+    assert l1 < 0.92 * l0

@@ -1,0 +1,182 @@
+"""Benchmark: optimisation steps/s of the per-pixel stochastic gradient
+estimator at the paper's scale on one MI355X.
+
+One step = estimate_grad over every (pair, view) item (8 antithetic pairs x
+4 views of a 1024^2 render of a 46080-triangle mesh with 1024^2 albedo,
+normal and roughness maps, GGX shading, L2 loss) followed by the Adam step
+over all 7 409 158 parameters.  Inputs (parameters, targets) are resident in
+HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config paper]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "optimisation steps/s at 1024², 50K tris (batched vs plain); % of HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes of the fused raster/shade/loss/scatter kernel (k_tile):
+# per pixel-estimate the target pixel is read once (12 B: the only per-pixel
+# HBM input once the + and - renders stay on chip), and every contribution
+# (pixel-estimate, group) adds one int64 sum and one uint32 count (12 B).
+BYTES_PER_PIXEL_ESTIMATE = 12
+BYTES_PER_CONTRIBUTION = 12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny"])
+    ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="both", choices=["both", "batched", "plain"])
+    return ap.parse_args()
+
+
+def run_mode(ctx, sc, th, m, v, tg, eps, steps, warmup, tuning, api, torch):
+    ctx.set_tuning(*tuning)
+    Q, K = ctx.new_accumulators()
+    n_pairs = sc.n_pairs
+    t = 0
+
+    def one_step():
+        nonlocal t
+        t += 1
+        ctx.estimate_grad(th, sc.views, tg, sc.seed, t, n_pairs, eps, Q=Q, K=K)
+        ctx.step(th, m, v, t, Q, K, eps, n_pairs, kind=api.ADAM, averaging=api.AVG_COUNT, lr=sc.lr)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ctx.timing_read(reset=True)
+    ctx.timing_enable(True)
+    # contributions per step (sum of K) measured once, outside the timed loop
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        one_step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.timing_enable(False)
+    tm = ctx.timing_read(reset=True)
+    ev_ms = start.elapsed_time(stop)
+    # one extra estimate to count contributions (sum of K) of a step
+    Q2, K2 = ctx.new_accumulators()
+    ctx.estimate_grad(th, sc.views, tg, sc.seed, t + 1, n_pairs, eps, Q=Q2, K=K2)
+    torch.cuda.synchronize()
+    contributions = int(K2.to(torch.int64).sum().item())
+    return {"ms_per_step": ev_ms / steps, "wall_ms_per_step": 1e3 * wall / steps, "timing": tm,
+            "contributions_per_step": contributions}
+
+
+def cpu_baseline(sc, n_items):
+    import numpy as np
+
+    import oracle
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    views = sc.views
+    items = [(n, v) for n in range(sc.n_pairs) for v in range(len(views))][:n_items]
+    targets = [o.render(sc.flat_params(True), vw)[0] for vw in views]
+    t0 = time.perf_counter()
+    Q = np.zeros(o.d, np.int64)
+    K = np.zeros(o.G, np.uint32)
+    for (n, v) in items:
+        # the oracle's estimate of one (pair, view) item: pair n via a sign table
+        s = oracle.signs(sc.seed, 1, n, 0, o.d)[None]
+        o.estimate(theta, [views[v]], [targets[v]], sc.seed, 1, 1, sc.eps, signs_=s, Q=Q, K=K)
+    t_items = time.perf_counter() - t0
+    th = theta.copy()
+    m = np.zeros(o.d, np.float32)
+    vv = np.zeros(o.d, np.float32)
+    t1 = time.perf_counter()
+    o.step(th, m, vv, 1, Q, K, sc.eps, sc.n_pairs, kind=0, averaging=0, lr=sc.lr)
+    t_step = time.perf_counter() - t1
+    total_items = sc.n_pairs * len(views)
+    sec_per_step = t_items / len(items) * total_items + t_step
+    return {"value": 1.0 / sec_per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(items)} of {total_items} (pair, view) items of one step plus one full Adam "
+                      f"step, single-threaded, extrapolated to a whole step ({sec_per_step:.1f} s/step)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2404_09758_amd import api, scenes
+    sc = scenes.CONFIGS[args.config]()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = api.Context(sc, dev, tuning=(16, 256, 0))
+    th0 = torch.tensor(sc.flat_params(), device=dev)
+    tgt_th = torch.tensor(sc.flat_params(True), device=dev)
+    tg = torch.cat([ctx.render(tgt_th, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views])
+    eps = sc.eps
+    px_per_step = sc.n_pairs * sum(v.width * v.height for v in sc.views)
+    results = {}
+    modes = {"batched": (16, 256, 0), "plain": (16, 256, 1)}
+    order = ["batched", "plain"] if args.mode == "both" else [args.mode]
+    for name in order:
+        th = th0.clone()
+        m = torch.zeros_like(th)
+        v = torch.zeros_like(th)
+        results[name] = run_mode(ctx, sc, th, m, v, tg, eps, args.steps, args.warmup, modes[name], api, torch)
+    main_mode = order[0]
+    r = results[main_mode]
+    tm = r["timing"]
+    tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
+    launches_per_step = tm["tile_launches"] / args.steps
+    alg_bytes_launch = (BYTES_PER_PIXEL_ESTIMATE * px_per_step
+                        + BYTES_PER_CONTRIBUTION * r["contributions_per_step"]) / launches_per_step
+    achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": 1e3 / r["ms_per_step"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {sc.views[0].width}x{sc.views[0].height} px, "
+                               f"{sc.n_tris} tris, {len(sc.views)} views x {sc.n_pairs} pairs, "
+                               f"d={sc.n_params}, {['unlit', 'lambert', 'ggx'][sc.shading]}",
+                   "mode": main_mode, "tile_px": 16, "bin_capacity": 256,
+                   "pixel_estimates_per_step": px_per_step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tile", "kernel_avg_ms": tile_avg_ms,
+                     "alg_bytes_per_launch": alg_bytes_launch},
+        "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")},
+        "pixel_estimates_per_s": px_per_step * 1e3 / r["ms_per_step"],
+    }
+    for name, rr in results.items():
+        out[f"{name}_steps_per_s"] = 1e3 / rr["ms_per_step"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_items)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

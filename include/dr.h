@@ -1,0 +1,196 @@
+/* dr.h -- per-pixel stochastic gradient estimator for MI355X (gfx950).
+ *
+ * C ABI of the library that turns a non-differentiable rasterizer into a
+ * differentiable one by stochastic finite differences evaluated per pixel
+ * (Deliot, Heitz, Belcour 2024).  The operations follow the paper's
+ * statement of the problem: a scene theta in R^d (geometry and textures,
+ * Sec. 4.1 / Table 1) is rendered to an image I(theta); the objective is the
+ * L2 error f = || I(theta) - I ||^2 against a target; its gradient is
+ * estimated with Eq. 8 (one antithetic pair of Rademacher perturbations,
+ * each pixel's loss difference credited only to the parameters that pixel
+ * used) and averaged over N pairs (Eq. 9) before a descent step (Sec. 5).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers owned by the caller (the library
+ *    never frees them), contiguous, 4-byte aligned (8 for int64), on the
+ *    GPU the context was created on.  Struct arguments are host memory and
+ *    are copied before the call returns.
+ *  - Calls are asynchronous on the context's HIP stream; results are ready
+ *    once that stream is synchronised.  dr_stats synchronises it.
+ *  - Errors are returned as dr_status codes (never aborts or exceptions);
+ *    dr_last_error gives the message of the last failing call.  An invalid
+ *    argument is detected on the host and nothing is launched.
+ *  - A context serves one stream and is not thread-safe; calls on one
+ *    context must not overlap.
+ *
+ * Flat parameter layout (shared by theta, Q, the Adam moments and the
+ * signs):  [ positions V x 3 (x,y,z) | texture 0 (H0,W0,C0) | texture 1 |
+ * texture 2 ], row-major texels, channels innermost.  Blocks: 0 =
+ * positions, 1 + t = texture t.  Textures: 0 albedo (3 channels), 1
+ * tangent-space normal map (3), 2 roughness (1).
+ *
+ * Contribution groups (the unit of the counts K): one group per vertex,
+ * then one per texel of each distinct texture resolution ("texel class",
+ * numbered in order of first appearance): textures of equal resolution
+ * share their texel groups because a sample reads the same texel
+ * coordinates in all of them.
+ */
+#ifndef DR_H
+#define DR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DR_MAX_TEX 3
+#define DR_MAX_VIEWS 16
+#define DR_BG_ID 0xFFFFFFFFu
+
+typedef enum {
+    DR_OK = 0,
+    DR_E_INVALID = -1,      /* bad argument, detected on the host           */
+    DR_E_OOM = -2,          /* device allocation failed                      */
+    DR_E_HIP = -3,          /* HIP runtime or launch error                   */
+    DR_E_UNSUPPORTED = -4   /* valid but not supported by this build         */
+} dr_status;
+
+enum { DR_UNLIT = 0, DR_LAMBERT = 1, DR_GGX = 2 };
+enum { DR_TEX_FOOTPRINT = 0, DR_TEX_NEAREST = 1 };
+enum { DR_AVG_COUNT = 0, DR_AVG_PAIRS = 1 };
+enum { DR_ADAM = 0, DR_SGD = 1 };
+
+typedef struct dr_ctx dr_ctx;
+
+/* Fixed scene data.  tri and corner_uv are device pointers that must stay
+ * valid for the life of the context. */
+typedef struct {
+    int32_t n_verts, n_tris;
+    const int32_t* tri;          /* [F,3] vertex indices                      */
+    const float* corner_uv;      /* [F,3,2] per-corner texture coordinates    */
+    int32_t n_tex;               /* 0..3                                      */
+    int32_t tex_w[DR_MAX_TEX], tex_h[DR_MAX_TEX], tex_c[DR_MAX_TEX];
+    int32_t shading;             /* DR_UNLIT | DR_LAMBERT | DR_GGX            */
+    int32_t tex_mode;            /* DR_TEX_FOOTPRINT | DR_TEX_NEAREST         */
+    float light_dir[3];          /* unit vector towards the light             */
+    float light_rgb[3];
+    float ambient, diffuse;
+} dr_scene;
+
+/* A camera: clip = view_proj * [x y z 1]^T (row-major); pixel (0,0) is the
+ * top-left.  Vertices with clip w < near_w cull their triangles. */
+typedef struct {
+    int32_t width, height;
+    float view_proj[16];
+    float cam_pos[3];
+    float near_w;
+} dr_view;
+
+/* Launch shape.  Raster tiles are tile_px (8, 16 or 32) pixels square,
+ * each with a bin of bin_capacity triangles; a tile whose bin overflows
+ * falls back to testing every triangle.  items_per_launch is the number of
+ * (pair, view) items one raster launch covers: 1 = one launch per item
+ * ("plain"), 0 = every item of the call in one launch ("batched").
+ * Results never depend on these values. */
+typedef struct {
+    int32_t tile_px;
+    int32_t bin_capacity;
+    int32_t items_per_launch;
+} dr_tuning;
+
+/* A perturbation of theta (Alg. 1): theta + sign * s (.) eps, with s the
+ * Rademacher vector of (seed, step, pair, scene_index). */
+typedef struct {
+    uint64_t seed;
+    uint32_t step, pair, scene_index;
+    int32_t sign;                /* +1 or -1                                  */
+    float eps[1 + DR_MAX_TEX];   /* per block; 0 leaves the block unperturbed */
+} dr_perturb;
+
+typedef struct {
+    int32_t kind;                /* DR_ADAM | DR_SGD                          */
+    int32_t averaging;           /* DR_AVG_COUNT | DR_AVG_PAIRS               */
+    float lr[1 + DR_MAX_TEX];    /* per block                                 */
+    float beta1, beta2, eps_hat;
+} dr_optim;
+
+typedef struct {
+    uint64_t tile_overflows;     /* (tile, render) bins that overflowed       */
+    uint64_t saturations;        /* loss differences clamped to |delta| = 32  */
+    uint64_t nonfinite;          /* NaN differences dropped; non-finite
+                                    gradients skipped by dr_step              */
+} dr_stats_t;
+
+/* Create a context for one scene on the current HIP device; stream is a
+ * hipStream_t (NULL = default stream); tune NULL picks 16 px tiles, 256
+ * triangles per bin and one launch per item. */
+dr_status dr_create(dr_ctx** out, const dr_scene* scene, const dr_tuning* tune, void* stream);
+dr_status dr_destroy(dr_ctx* ctx);
+dr_status dr_set_stream(dr_ctx* ctx, void* stream);
+dr_status dr_set_tuning(dr_ctx* ctx, const dr_tuning* tune);
+int64_t dr_param_count(const dr_ctx* ctx);       /* d                         */
+int64_t dr_group_count(const dr_ctx* ctx);       /* number of groups G        */
+
+/* The rasterizer R extended with ID and UV buffers (Sec. 4.4): render theta
+ * (perturbed when pert != NULL) from one view.  rgb [H,W,3] float, id [H,W]
+ * uint32 (DR_BG_ID where no triangle covers the pixel centre), uv [H,W,2]
+ * float (0 on background); any output may be NULL. */
+dr_status dr_render(dr_ctx* ctx, const float* theta, const dr_view* view, const dr_perturb* pert,
+                    float* rgb, uint32_t* id, float* uv);
+
+/* The sign vector of one pair (Alg. 1, randomsign): bit i of the uint32
+ * words bits[ceil(d/32)] set means s_i = -1. */
+dr_status dr_signs(dr_ctx* ctx, uint64_t seed, uint32_t step, uint32_t pair, uint32_t scene_index,
+                   uint32_t* bits);
+
+/* Eq. 8 for n_pairs antithetic pairs over n_views views (Eq. 9 numerator),
+ * accumulated into the caller's buffers:
+ *   Q [d] int64:  Q_i += s_i * round(delta_p * 2^32)   over every pixel p
+ *                 (of every pair and view) whose contribution set holds i;
+ *   K [G] uint32: K_g += 1 per (pair, view, pixel) whose set holds group g.
+ * The contribution set of a pixel is the union over the two renders of
+ * the visible triangle's three vertices (ID buffer) and the texels its
+ * sample read (UV buffer).  targets: device, the views' [H,W,3] float
+ * images concatenated in view order.  eps: host, per block (>= 0). */
+dr_status dr_estimate_grad(dr_ctx* ctx, const float* theta, const dr_view* views, int32_t n_views,
+                           const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                           const float* eps, int64_t* Q, uint32_t* K);
+
+/* Decode Q, K into float gradients: g_i = Q_i 2^-32 / (2 eps_i D_i) with
+ * D_i = K of the parameter's group (DR_AVG_COUNT) or n_pairs (DR_AVG_PAIRS,
+ * Eq. 9); 0 where eps_i = 0 or D_i = 0.  grad [d] float. */
+dr_status dr_decode_grad(dr_ctx* ctx, const int64_t* Q, const uint32_t* K, const float* eps,
+                         int32_t averaging, int32_t n_pairs, float* grad);
+
+/* The descent step (Sec. 5, shader D): decode as dr_decode_grad, then Adam
+ * (bias-corrected with step t >= 1) or SGD on theta with per-block learning
+ * rates; parameters with eps_i = 0, or (count averaging) with K = 0, are
+ * not updated.  m, v [d] float are the Adam moments.  Q and K are zeroed. */
+dr_status dr_step(dr_ctx* ctx, float* theta, float* m, float* v, uint32_t t, int64_t* Q, uint32_t* K,
+                  const float* eps, int32_t n_pairs, const dr_optim* opt);
+
+/* Per-kernel timing: while enabled, HIP events are recorded on the
+ * context's stream around every launch of the estimator's kernels;
+ * dr_timing_read synchronises the stream and returns the summed durations
+ * (milliseconds) and launch counts since the last reset (reset != 0 clears
+ * them after reading). */
+typedef struct {
+    double signs_ms, setup_ms, tile_ms, fold_ms, step_ms;
+    int64_t signs_launches, setup_launches, tile_launches, fold_launches, step_launches;
+} dr_timing_t;
+
+dr_status dr_timing_enable(dr_ctx* ctx, int enable);
+dr_status dr_timing_read(dr_ctx* ctx, dr_timing_t* out, int reset);
+
+/* Device-side condition counters since the last reset (synchronises). */
+dr_status dr_stats(dr_ctx* ctx, dr_stats_t* out);
+dr_status dr_reset_stats(dr_ctx* ctx);
+
+const char* dr_status_str(dr_status s);
+const char* dr_last_error(const dr_ctx* ctx);     /* "" when none; ctx may be NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,646 @@
+// dr_api.hip -- host side of the C ABI declared in include/dr.h.
+//
+// Owns the per-context scratch memory (sign bits, triangle records, bins,
+// per-pair group sums), validates every argument on the host before
+// launching, and orders the kernels of dr_kernels.hip on the context's
+// stream.  Scratch buffers grow on demand and are reused; the bin counters
+// and the per-pair sums are left zeroed by the kernels that consume them,
+// so no clearing pass is needed between calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dr.h"
+#include "dr_launch.h"
+
+struct dr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    dr_scene hs{};
+    DScene sc{};
+    dr_tuning tune{16, 256, 1};
+    std::string err;
+    TriR* recR = nullptr;
+    TriS* recS = nullptr;
+    long long rec_slots = 0;
+    unsigned* counts = nullptr;
+    unsigned* bins = nullptr;
+    long long tile_slots = 0;       // slots * max_tiles allocated
+    long long bin_entries = 0;      // tile_slots * cap allocated
+    long long* R = nullptr;
+    long long R_pairs = 0;
+    uint32_t* bits = nullptr;
+    long long bits_pairs = 0;
+    unsigned long long* stats = nullptr;
+    // timing: event pairs recorded around launches while enabled
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<hipEvent_t> ev_pending[5][2];     // [kind][begin/end]
+};
+
+enum { K_SIGNS = 0, K_SETUP = 1, K_TILE = 2, K_FOLD = 3, K_STEP = 4 };
+
+static hipEvent_t take_event(dr_ctx* c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one launch, bracketed by events when timing is enabled.
+template <typename F>
+static hipError_t timed(dr_ctx* c, int kind, F launch) {
+    if (!c->timing) return launch();
+    hipEvent_t b = take_event(c), e = take_event(c);
+    if (!b || !e) return hipErrorOutOfMemory;
+    hipError_t r = hipEventRecord(b, c->stream);
+    if (r != hipSuccess) return r;
+    r = launch();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(e, c->stream);
+    c->ev_pending[kind][0].push_back(b);
+    c->ev_pending[kind][1].push_back(e);
+    return r;
+}
+
+static dr_status fail(dr_ctx* c, dr_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(c, expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail((c), DR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
+
+static dr_status device_guard(dr_ctx* c) {
+    int cur = -1;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != c->device) HIPCHK(c, hipSetDevice(c->device));
+    return DR_OK;
+}
+
+// ------------------------------------------------------------ scratch --
+
+template <typename T>
+static dr_status grow(dr_ctx* c, T** p, long long* have, long long need, size_t elem, bool zero) {
+    if (need <= *have) return DR_OK;
+    if (*p) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipFree(*p));
+        *p = nullptr;
+        *have = 0;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)need * elem) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DR_E_OOM, "hipMalloc of " + std::to_string((size_t)need * elem) + " bytes failed");
+    }
+    if (zero) HIPCHK(c, hipMemsetAsync(q, 0, (size_t)need * elem, c->stream));
+    *p = (T*)q;
+    *have = need;
+    return DR_OK;
+}
+
+static dr_status ensure_raster(dr_ctx* c, long long slots, int max_tiles) {
+    long long have = c->rec_slots;
+    dr_status s = grow(c, &c->recR, &have, slots * c->sc.n_tris, sizeof(TriR), false);
+    if (s) return s;
+    have = c->rec_slots;
+    s = grow(c, &c->recS, &have, slots * c->sc.n_tris, sizeof(TriS), false);
+    if (s) return s;
+    if (slots * c->sc.n_tris > c->rec_slots) c->rec_slots = slots * c->sc.n_tris;
+    s = grow(c, &c->counts, &c->tile_slots, slots * (long long)max_tiles, sizeof(unsigned), true);
+    if (s) return s;
+    return grow(c, &c->bins, &c->bin_entries, slots * (long long)max_tiles * c->tune.bin_capacity,
+                sizeof(unsigned), false);
+}
+
+// ---------------------------------------------------------- validation --
+
+static dr_status check_view(dr_ctx* c, const dr_view* v, int tile) {
+    if (!v) return fail(c, DR_E_INVALID, "view is NULL");
+    if (v->width < 1 || v->height < 1 || v->width > 16384 || v->height > 16384)
+        return fail(c, DR_E_INVALID, "view size must be in [1, 16384]");
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(v->view_proj[i])) return fail(c, DR_E_INVALID, "view_proj is not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(v->cam_pos[i])) return fail(c, DR_E_INVALID, "cam_pos is not finite");
+    if (!std::isfinite(v->near_w)) return fail(c, DR_E_INVALID, "near_w is not finite");
+    (void)tile;
+    return DR_OK;
+}
+
+static DView make_dview(const dr_view& v, int tile, long long tgt_off) {
+    DView d;
+    d.W = v.width;
+    d.H = v.height;
+    std::memcpy(d.M, v.view_proj, sizeof(d.M));
+    std::memcpy(d.cam, v.cam_pos, sizeof(d.cam));
+    d.near_w = v.near_w;
+    d.tiles_x = (v.width + tile - 1) / tile;
+    d.tiles_y = (v.height + tile - 1) / tile;
+    d.tgt_off = tgt_off;
+    return d;
+}
+
+static dr_status check_eps(dr_ctx* c, const float* eps) {
+    if (!eps) return fail(c, DR_E_INVALID, "eps is NULL");
+    for (int b = 0; b < 1 + c->sc.n_tex; ++b)
+        if (!finite_nonneg(eps[b])) return fail(c, DR_E_INVALID, "eps must be finite and >= 0");
+    return DR_OK;
+}
+
+static dr_status check_tuning(dr_ctx* c, const dr_tuning* t) {
+    if (t->tile_px != 8 && t->tile_px != 16 && t->tile_px != 32)
+        return fail(c, DR_E_INVALID, "tile_px must be 8, 16 or 32");
+    if (t->bin_capacity < 1 || t->bin_capacity > (1 << 20))
+        return fail(c, DR_E_INVALID, "bin_capacity must be in [1, 2^20]");
+    if (t->items_per_launch < 0) return fail(c, DR_E_INVALID, "items_per_launch must be >= 0");
+    return DR_OK;
+}
+
+// ------------------------------------------------------------- create --
+
+extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning* tune, void* stream) {
+    if (!out || !s) return DR_E_INVALID;
+    *out = nullptr;
+    if (s->n_verts < 1 || s->n_tris < 1) return DR_E_INVALID;
+    if (!s->tri || !s->corner_uv) return DR_E_INVALID;
+    if (s->n_tex < 0 || s->n_tex > DR_MAX_TEX) return DR_E_INVALID;
+    if (s->shading < DR_UNLIT || s->shading > DR_GGX) return DR_E_INVALID;
+    if (s->tex_mode != DR_TEX_FOOTPRINT && s->tex_mode != DR_TEX_NEAREST) return DR_E_INVALID;
+    if (s->shading != DR_UNLIT && s->n_tex < 1) return DR_E_INVALID;
+    long long d = 3ll * s->n_verts;
+    for (int t = 0; t < s->n_tex; ++t) {
+        if (s->tex_w[t] < 1 || s->tex_h[t] < 1 || s->tex_w[t] > 32768 || s->tex_h[t] > 32768) return DR_E_INVALID;
+        int want = (t == 2) ? 1 : 3;
+        if (s->tex_c[t] != want) return DR_E_INVALID;
+        d += (long long)s->tex_w[t] * s->tex_h[t] * s->tex_c[t];
+    }
+    if (d >= (1ll << 36)) return DR_E_INVALID;
+    dr_ctx* c = new (std::nothrow) dr_ctx();
+    if (!c) return DR_E_OOM;
+    c->hs = *s;
+    c->stream = (hipStream_t)stream;
+    if (tune) {
+        if (check_tuning(c, tune)) {
+            delete c;
+            return DR_E_INVALID;
+        }
+        c->tune = *tune;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return DR_E_HIP;
+    }
+    DScene& sc = c->sc;
+    sc.n_verts = s->n_verts;
+    sc.n_tris = s->n_tris;
+    sc.tri = s->tri;
+    sc.cuv = s->corner_uv;
+    sc.n_tex = s->n_tex;
+    long long off = 3ll * s->n_verts;
+    long long goff = s->n_verts;
+    sc.n_cls = 0;
+    for (int t = 0; t < DRD_MAX_TEX; ++t) {
+        sc.tex_w[t] = sc.tex_h[t] = sc.tex_c[t] = 0;
+        sc.tex_off[t] = 0;
+        sc.tex_cls[t] = -1;
+        sc.cls_w[t] = sc.cls_h[t] = 0;
+        sc.cls_goff[t] = 0;
+    }
+    for (int t = 0; t < s->n_tex; ++t) {
+        sc.tex_w[t] = s->tex_w[t];
+        sc.tex_h[t] = s->tex_h[t];
+        sc.tex_c[t] = s->tex_c[t];
+        sc.tex_off[t] = off;
+        off += (long long)s->tex_w[t] * s->tex_h[t] * s->tex_c[t];
+        int cls = -1;
+        for (int k = 0; k < sc.n_cls; ++k)
+            if (sc.cls_w[k] == s->tex_w[t] && sc.cls_h[k] == s->tex_h[t]) cls = k;
+        if (cls < 0) {
+            cls = sc.n_cls++;
+            sc.cls_w[cls] = s->tex_w[t];
+            sc.cls_h[cls] = s->tex_h[t];
+            sc.cls_goff[cls] = goff;
+            goff += (long long)s->tex_w[t] * s->tex_h[t];
+        }
+        sc.tex_cls[t] = cls;
+    }
+    sc.shading = s->shading;
+    sc.tex_mode = s->tex_mode;
+    for (int i = 0; i < 3; ++i) {
+        sc.light[i] = s->light_dir[i];
+        sc.light_rgb[i] = s->light_rgb[i];
+    }
+    sc.ambient = s->ambient;
+    sc.diffuse = s->diffuse;
+    sc.d = off;
+    sc.G = goff;
+    sc.words = (int)((off + 31) / 32);
+    if (hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->stats) (void)hipFree(c->stats);
+        delete c;
+        return DR_E_OOM;
+    }
+    // every vertex index must address the vertex array
+    unsigned long long bad = 0;
+    bool ok = launch_check_tri(c->stream, s->tri, 3ll * s->n_tris, s->n_verts, c->stats + 3) == hipSuccess &&
+              hipMemcpyAsync(&bad, c->stats + 3, sizeof(bad), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+              hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!ok || bad != 0) {
+        (void)hipGetLastError();
+        (void)hipFree(c->stats);
+        delete c;
+        return ok ? DR_E_INVALID : DR_E_HIP;
+    }
+    *out = c;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_destroy(dr_ctx* c) {
+    if (!c) return DR_E_INVALID;
+    (void)hipStreamSynchronize(c->stream);
+    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int k = 0; k < 5; ++k)
+        for (int j = 0; j < 2; ++j)
+            for (hipEvent_t e : c->ev_pending[k][j]) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    delete c;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_set_stream(dr_ctx* c, void* stream) {
+    if (!c) return DR_E_INVALID;
+    c->stream = (hipStream_t)stream;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_set_tuning(dr_ctx* c, const dr_tuning* t) {
+    if (!c || !t) return fail(c, DR_E_INVALID, "NULL argument");
+    dr_status s = check_tuning(c, t);
+    if (s) return s;
+    if (t->bin_capacity != c->tune.bin_capacity) {
+        // the bin array is indexed with the capacity: reallocate on next use
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->bins) HIPCHK(c, hipFree(c->bins));
+        c->bins = nullptr;
+        c->bin_entries = 0;
+    }
+    c->tune = *t;
+    return DR_OK;
+}
+
+extern "C" int64_t dr_param_count(const dr_ctx* c) { return c ? c->sc.d : -1; }
+extern "C" int64_t dr_group_count(const dr_ctx* c) { return c ? c->sc.G : -1; }
+
+// -------------------------------------------------------------- signs --
+
+static dr_status ensure_bits(dr_ctx* c, long long pairs) {
+    return grow(c, &c->bits, &c->bits_pairs, pairs, (size_t)c->sc.words * sizeof(uint32_t), false);
+}
+
+extern "C" dr_status dr_signs(dr_ctx* c, uint64_t seed, uint32_t step, uint32_t pair, uint32_t scene,
+                              uint32_t* bits) {
+    if (!c) return DR_E_INVALID;
+    if (!bits) return fail(c, DR_E_INVALID, "bits is NULL");
+    dr_status s = device_guard(c);
+    if (s) return s;
+    HIPCHK(c, timed(c, K_SIGNS, [&] { return launch_signs(c->stream, seed, step, pair, scene, c->sc.d, c->sc.words, 1, bits); }));
+    return DR_OK;
+}
+
+// ------------------------------------------------------------- render --
+
+extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* view, const dr_perturb* pert,
+                               float* rgb, uint32_t* id, float* uv) {
+    if (!c) return DR_E_INVALID;
+    if (!theta) return fail(c, DR_E_INVALID, "theta is NULL");
+    int tile = c->tune.tile_px;
+    dr_status s = check_view(c, view, tile);
+    if (s) return s;
+    if (pert) {
+        if (pert->sign != 1 && pert->sign != -1) return fail(c, DR_E_INVALID, "pert->sign must be +1 or -1");
+        s = check_eps(c, pert->eps);
+        if (s) return s;
+    }
+    s = device_guard(c);
+    if (s) return s;
+    DView dv = make_dview(*view, tile, 0);
+    int max_tiles = dv.tiles_x * dv.tiles_y;
+    s = ensure_raster(c, 1, max_tiles);
+    if (s) return s;
+    DPert dp;
+    dp.bits = nullptr;
+    for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = 0.0f;
+    float sg = 1.0f;
+    if (pert) {
+        s = ensure_bits(c, 1);
+        if (s) return s;
+        HIPCHK(c, timed(c, K_SIGNS, [&] {
+            return launch_signs(c->stream, pert->seed, pert->step, pert->pair, pert->scene_index, c->sc.d,
+                                c->sc.words, 1, c->bits);
+        }));
+        dp.bits = c->bits;
+        for (int b = 0; b < 1 + c->sc.n_tex; ++b) dp.eps[b] = pert->eps[b];
+        sg = (float)pert->sign;
+    }
+    SetupArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.sc = c->sc;
+    sa.views.v[0] = dv;
+    sa.pert = dp;
+    sa.theta = theta;
+    sa.n_views = 1;
+    sa.item0 = 0;
+    sa.nsign = 1;
+    sa.sgn[0] = sg;
+    sa.sgn[1] = sg;
+    sa.tile = tile;
+    sa.cap = c->tune.bin_capacity;
+    sa.max_tiles = max_tiles;
+    sa.recR = c->recR;
+    sa.recS = c->recS;
+    sa.counts = c->counts;
+    sa.bins = c->bins;
+    HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, 1); }));
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.sc = c->sc;
+    ta.views.v[0] = dv;
+    ta.pert = dp;
+    ta.theta = theta;
+    ta.n_views = 1;
+    ta.item0 = 0;
+    ta.nsign = 1;
+    ta.sgn[0] = sg;
+    ta.sgn[1] = sg;
+    ta.cap = c->tune.bin_capacity;
+    ta.max_tiles = max_tiles;
+    ta.recR = c->recR;
+    ta.recS = c->recS;
+    ta.counts = c->counts;
+    ta.bins = c->bins;
+    ta.stats = c->stats;
+    ta.out_rgb = rgb;
+    ta.out_id = id;
+    ta.out_uv = uv;
+    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, true, 1, max_tiles); }));
+    return DR_OK;
+}
+
+// ----------------------------------------------------------- estimate --
+
+extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                                      const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                      const float* eps, int64_t* Q, uint32_t* K) {
+    if (!c) return DR_E_INVALID;
+    if (!theta || !targets || !Q || !K || !views) return fail(c, DR_E_INVALID, "NULL array argument");
+    if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
+    if (n_pairs < 1 || n_pairs > 65535) return fail(c, DR_E_INVALID, "n_pairs must be in [1, 65535]");
+    int tile = c->tune.tile_px;
+    dr_status s = check_eps(c, eps);
+    if (s) return s;
+    DViews dv;
+    std::memset(&dv, 0, sizeof(dv));
+    long long tgt_off = 0;
+    int max_tiles = 1;
+    for (int v = 0; v < n_views; ++v) {
+        s = check_view(c, &views[v], tile);
+        if (s) return s;
+        dv.v[v] = make_dview(views[v], tile, tgt_off);
+        tgt_off += 3ll * views[v].width * views[v].height;
+        max_tiles = std::max(max_tiles, dv.v[v].tiles_x * dv.v[v].tiles_y);
+    }
+    s = device_guard(c);
+    if (s) return s;
+    long long items = (long long)n_pairs * n_views;
+    long long per = c->tune.items_per_launch == 0 ? items : std::min<long long>(items, c->tune.items_per_launch);
+    per = std::min<long long>(per, 32767);      // grid y of the setup launch is 2 * items <= 65535
+    s = ensure_raster(c, 2 * per, max_tiles);
+    if (s) return s;
+    s = ensure_bits(c, n_pairs);
+    if (s) return s;
+    s = grow(c, &c->R, &c->R_pairs, n_pairs, (size_t)c->sc.G * sizeof(long long), true);
+    if (s) return s;
+
+    DPert dp;
+    dp.bits = c->bits;
+    for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = (b < 1 + c->sc.n_tex) ? eps[b] : 0.0f;
+    HIPCHK(c, timed(c, K_SIGNS, [&] { return launch_signs(c->stream, seed, step, 0u, 0u, c->sc.d, c->sc.words, n_pairs, c->bits); }));
+
+    SetupArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.sc = c->sc;
+    sa.views = dv;
+    sa.pert = dp;
+    sa.theta = theta;
+    sa.n_views = n_views;
+    sa.nsign = 2;
+    sa.sgn[0] = 1.0f;
+    sa.sgn[1] = -1.0f;
+    sa.tile = tile;
+    sa.cap = c->tune.bin_capacity;
+    sa.max_tiles = max_tiles;
+    sa.recR = c->recR;
+    sa.recS = c->recS;
+    sa.counts = c->counts;
+    sa.bins = c->bins;
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.sc = c->sc;
+    ta.views = dv;
+    ta.pert = dp;
+    ta.theta = theta;
+    ta.n_views = n_views;
+    ta.nsign = 2;
+    ta.sgn[0] = 1.0f;
+    ta.sgn[1] = -1.0f;
+    ta.cap = c->tune.bin_capacity;
+    ta.max_tiles = max_tiles;
+    ta.recR = c->recR;
+    ta.recS = c->recS;
+    ta.counts = c->counts;
+    ta.bins = c->bins;
+    ta.stats = c->stats;
+    ta.targets = targets;
+    ta.R = c->R;
+    ta.K = K;
+    ta.act_pos = eps[0] != 0.0f;
+    ta.any_act = ta.act_pos;
+    for (int t = 0; t < c->sc.n_tex; ++t)
+        if (eps[1 + t] != 0.0f) {
+            ta.act_cls[c->sc.tex_cls[t]] = 1;
+            ta.any_act = 1;
+        }
+    for (long long i0 = 0; i0 < items; i0 += per) {
+        int n = (int)std::min(per, items - i0);
+        sa.item0 = (int)i0;
+        ta.item0 = (int)i0;
+        HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
+        HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, false, n, max_tiles); }));
+    }
+    FoldArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.sc = c->sc;
+    fa.R = c->R;
+    fa.bits = c->bits;
+    fa.n_pairs = n_pairs;
+    for (int b = 0; b <= DRD_MAX_TEX; ++b) fa.eps[b] = dp.eps[b];
+    fa.Q = (long long*)Q;
+    HIPCHK(c, timed(c, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    return DR_OK;
+}
+
+// ------------------------------------------------------- decode / step --
+
+static dr_status step_common(dr_ctx* c, float* theta, float* m, float* v, uint32_t t, int64_t* Q, uint32_t* K,
+                             const float* eps, int32_t n_pairs, const dr_optim* o, int averaging, float* grad) {
+    dr_status s = check_eps(c, eps);
+    if (s) return s;
+    if (averaging != DR_AVG_COUNT && averaging != DR_AVG_PAIRS) return fail(c, DR_E_INVALID, "bad averaging");
+    if (averaging == DR_AVG_PAIRS && n_pairs < 1) return fail(c, DR_E_INVALID, "n_pairs must be >= 1");
+    s = device_guard(c);
+    if (s) return s;
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sc = c->sc;
+    for (int b = 0; b < 1 + c->sc.n_tex; ++b) a.eps[b] = eps[b];
+    a.averaging = averaging;
+    a.n_pairs = n_pairs;
+    a.Q = (long long*)Q;
+    a.K = K;
+    a.stats = c->stats;
+    if (grad) {
+        a.decode_only = 1;
+        a.grad = grad;
+    } else {
+        a.kind = o->kind;
+        for (int b = 0; b < 1 + c->sc.n_tex; ++b) a.lr[b] = o->lr[b];
+        a.b1 = o->beta1;
+        a.b2 = o->beta2;
+        a.omb1 = (float)(1.0 - (double)o->beta1);
+        a.omb2 = (float)(1.0 - (double)o->beta2);
+        a.bc1 = (float)(1.0 - std::pow((double)o->beta1, (double)t));
+        a.bc2 = (float)(1.0 - std::pow((double)o->beta2, (double)t));
+        a.eps_hat = o->eps_hat;
+        a.theta = theta;
+        a.m = m;
+        a.v = v;
+    }
+    HIPCHK(c, timed(c, K_STEP, [&] { return launch_step(c->stream, a); }));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_decode_grad(dr_ctx* c, const int64_t* Q, const uint32_t* K, const float* eps,
+                                    int32_t averaging, int32_t n_pairs, float* grad) {
+    if (!c) return DR_E_INVALID;
+    if (!Q || !K || !grad) return fail(c, DR_E_INVALID, "NULL array argument");
+    return step_common(c, nullptr, nullptr, nullptr, 1, (int64_t*)Q, (uint32_t*)K, eps, n_pairs, nullptr,
+                       averaging, grad);
+}
+
+extern "C" dr_status dr_step(dr_ctx* c, float* theta, float* m, float* v, uint32_t t, int64_t* Q, uint32_t* K,
+                             const float* eps, int32_t n_pairs, const dr_optim* o) {
+    if (!c) return DR_E_INVALID;
+    if (!theta || !Q || !K || !o) return fail(c, DR_E_INVALID, "NULL argument");
+    if (o->kind != DR_ADAM && o->kind != DR_SGD) return fail(c, DR_E_INVALID, "bad optimiser kind");
+    if (o->kind == DR_ADAM) {
+        if (!m || !v) return fail(c, DR_E_INVALID, "Adam needs m and v");
+        if (t < 1) return fail(c, DR_E_INVALID, "Adam step t must be >= 1");
+        if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f && o->beta2 >= 0.0f && o->beta2 < 1.0f))
+            return fail(c, DR_E_INVALID, "betas must be in [0, 1)");
+        if (!finite_nonneg(o->eps_hat)) return fail(c, DR_E_INVALID, "eps_hat must be finite and >= 0");
+    }
+    for (int b = 0; b < 1 + c->sc.n_tex; ++b)
+        if (!std::isfinite(o->lr[b])) return fail(c, DR_E_INVALID, "lr must be finite");
+    return step_common(c, theta, m, v, t, Q, K, eps, n_pairs, o, o->averaging, nullptr);
+}
+
+// ------------------------------------------------------------- timing --
+
+extern "C" dr_status dr_timing_enable(dr_ctx* c, int enable) {
+    if (!c) return DR_E_INVALID;
+    c->timing = enable != 0;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_timing_read(dr_ctx* c, dr_timing_t* out, int reset) {
+    if (!c || !out) return fail(c, DR_E_INVALID, "NULL argument");
+    dr_status s = device_guard(c);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t n[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 5; ++k) {
+        for (size_t i = 0; i < c->ev_pending[k][0].size(); ++i) {
+            float t = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&t, c->ev_pending[k][0][i], c->ev_pending[k][1][i]));
+            ms[k] += t;
+            n[k] += 1;
+        }
+        if (reset) {
+            for (int j = 0; j < 2; ++j) {
+                for (hipEvent_t e : c->ev_pending[k][j]) c->ev_free.push_back(e);
+                c->ev_pending[k][j].clear();
+            }
+        }
+    }
+    out->signs_ms = ms[K_SIGNS]; out->signs_launches = n[K_SIGNS];
+    out->setup_ms = ms[K_SETUP]; out->setup_launches = n[K_SETUP];
+    out->tile_ms = ms[K_TILE]; out->tile_launches = n[K_TILE];
+    out->fold_ms = ms[K_FOLD]; out->fold_launches = n[K_FOLD];
+    out->step_ms = ms[K_STEP]; out->step_launches = n[K_STEP];
+    return DR_OK;
+}
+
+// -------------------------------------------------------------- stats --
+
+extern "C" dr_status dr_stats(dr_ctx* c, dr_stats_t* out) {
+    if (!c || !out) return fail(c, DR_E_INVALID, "NULL argument");
+    dr_status s = device_guard(c);
+    if (s) return s;
+    unsigned long long h[4];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
+    out->tile_overflows = h[0];
+    out->saturations = h[1];
+    out->nonfinite = h[2];
+    return DR_OK;
+}
+
+extern "C" dr_status dr_reset_stats(dr_ctx* c) {
+    if (!c) return DR_E_INVALID;
+    dr_status s = device_guard(c);
+    if (s) return s;
+    HIPCHK(c, hipMemsetAsync(c->stats, 0, 4 * sizeof(unsigned long long), c->stream));
+    return DR_OK;
+}
+
+extern "C" const char* dr_status_str(dr_status s) {
+    switch (s) {
+        case DR_OK: return "ok";
+        case DR_E_INVALID: return "invalid argument";
+        case DR_E_OOM: return "out of device memory";
+        case DR_E_HIP: return "HIP error";
+        case DR_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* dr_last_error(const dr_ctx* c) { return c ? c->err.c_str() : ""; }

@@ -1,0 +1,346 @@
+// dr_device.h -- device-side data layout and per-pixel arithmetic of the
+// per-pixel stochastic gradient estimator (gfx950).
+//
+// Every floating-point expression is written with explicit parentheses
+// and compiled with -ffp-contract=off, so each result is the correctly
+// rounded fp32 value of the stated operation sequence; divisions and square
+// roots are the correctly rounded ones.  This fixed operation order is what
+// makes the triangle IDs, the loss differences and hence the fixed-point
+// gradient sums reproducible bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DRD_BG 0xFFFFFFFFu
+#define DRD_MAX_TEX 3
+#define DRD_MAX_VIEWS 16
+#define DRD_PI 3.14159265f
+#define DRD_INV_PI 0.318309886f
+
+// Scene constants, passed by value to every kernel.
+struct DScene {
+    int n_verts, n_tris;
+    const int* tri;             // [F,3]
+    const float* cuv;           // [F,3,2]
+    int n_tex;
+    int tex_w[DRD_MAX_TEX], tex_h[DRD_MAX_TEX], tex_c[DRD_MAX_TEX];
+    long long tex_off[DRD_MAX_TEX];      // first parameter of each texture
+    int tex_cls[DRD_MAX_TEX];            // texel class of each texture
+    int n_cls;
+    int cls_w[DRD_MAX_TEX], cls_h[DRD_MAX_TEX];
+    long long cls_goff[DRD_MAX_TEX];     // first group of each class
+    int shading, tex_mode;
+    float light[3], light_rgb[3], ambient, diffuse;
+    long long d, G;
+    int words;                           // ceil(d / 32) sign words per pair
+};
+
+struct DView {
+    int W, H;
+    float M[16];
+    float cam[3];
+    float near_w;
+    int tiles_x, tiles_y;
+    long long tgt_off;                   // first float of this view's target
+};
+
+struct DViews {
+    DView v[DRD_MAX_VIEWS];
+};
+
+// Perturbation of one launch: per-block eps and the sign bits of the pairs.
+struct DPert {
+    const uint32_t* bits;                // [pairs, words] or null (no perturbation)
+    float eps[1 + DRD_MAX_TEX];
+};
+
+// Raster half of a triangle record (64 B): snapped vertices in normalised
+// (positive-area) order, the depth plane, flags and the pixel bounding box.
+struct __align__(16) TriR {
+    int X[3], Y[3];
+    float z0, zx, zy;
+    unsigned flags;                      // bit0 valid, bit1+k top-left edge k, bit4 swapped
+    short bx0, by0, bx1, by1;            // inclusive pixel bbox, clamped to the view
+    long long area2;
+    int pad[2];
+};
+
+// Shading half (64 B): 1/w in normalised order, perturbed world positions
+// and vertex indices in the original corner order.
+struct __align__(16) TriS {
+    float iw[3];
+    float p[9];
+    int vid[3];
+    int pad;
+};
+
+static_assert(sizeof(TriR) == 64, "TriR layout");
+static_assert(sizeof(TriS) == 64, "TriS layout");
+
+#define TRI_VALID 1u
+#define TRI_SWAPPED 16u
+
+// ---------------------------------------------------------------- signs --
+
+__device__ __forceinline__ void philox4x64_10(unsigned long long c0, unsigned long long c1,
+                                              unsigned long long c2, unsigned long long c3,
+                                              unsigned long long k0, unsigned long long k1,
+                                              unsigned long long out[4]) {
+    const unsigned long long M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const unsigned long long W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        unsigned long long hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        unsigned long long hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        unsigned long long n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// theta_i perturbed by sgn * s_i * eps (one fp32 add or subtract).
+__device__ __forceinline__ float pval(const float* __restrict__ th, long long i, float e,
+                                      const uint32_t* __restrict__ pb, float sgn) {
+    float x = th[i];
+    if (pb == nullptr || e == 0.0f) return x;
+    unsigned w = pb[i >> 5];
+    float se = ((w >> (unsigned)(i & 31)) & 1u) ? -e : e;
+    return (sgn > 0.0f) ? (x + se) : (x - se);
+}
+
+__device__ __forceinline__ int sign_of(const uint32_t* __restrict__ pb, long long i) {
+    return ((pb[i >> 5] >> (unsigned)(i & 31)) & 1u) ? -1 : 1;
+}
+
+// ------------------------------------------------------------ geometry --
+
+struct Vtx {
+    int valid;
+    int X, Y;
+    float z, iw;
+};
+
+__device__ __forceinline__ Vtx xform(const DView& v, float x, float y, float z) {
+    const float* M = v.M;
+    float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+    float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+    float cz = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+    float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
+    Vtx o;
+    o.valid = 0; o.X = 0; o.Y = 0; o.z = 0.0f; o.iw = 0.0f;
+    if (!(cw >= v.near_w)) return o;
+    float nx = cx / cw, ny = cy / cw, nz = cz / cw;
+    float sx = (nx * 0.5f + 0.5f) * (float)v.W;
+    float sy = (0.5f - ny * 0.5f) * (float)v.H;
+    float fx = sx * 256.0f, fy = sy * 256.0f;
+    if (!(fabsf(fx) <= 4194304.0f) || !(fabsf(fy) <= 4194304.0f)) return o;
+    o.valid = 1;
+    o.X = (int)rintf(fx);
+    o.Y = (int)rintf(fy);
+    o.z = nz * 0.5f + 0.5f;
+    o.iw = 1.0f / cw;
+    return o;
+}
+
+// Edge k of a normalised triangle runs from vertex k+1 to vertex k+2.
+__device__ __forceinline__ long long edge_at(int xa, int ya, int xb, int yb, int px, int py) {
+    return (long long)(xb - xa) * (long long)(py - ya) - (long long)(yb - ya) * (long long)(px - xa);
+}
+
+__device__ __forceinline__ bool inside(const TriR& r, int px, int py, long long& e0, long long& e1,
+                                       long long& e2) {
+    e0 = edge_at(r.X[1], r.Y[1], r.X[2], r.Y[2], px, py);
+    e1 = edge_at(r.X[2], r.Y[2], r.X[0], r.Y[0], px, py);
+    e2 = edge_at(r.X[0], r.Y[0], r.X[1], r.Y[1], px, py);
+    bool ok0 = (e0 > 0) || (e0 == 0 && (r.flags & 2u));
+    bool ok1 = (e1 > 0) || (e1 == 0 && (r.flags & 4u));
+    bool ok2 = (e2 > 0) || (e2 == 0 && (r.flags & 8u));
+    return ok0 && ok1 && ok2;
+}
+
+__device__ __forceinline__ float depth_at(const TriR& r, int px, int py) {
+    float z = (r.z0 + r.zx * (float)(px - r.X[0])) + r.zy * (float)(py - r.Y[0]);
+    if (!(z > 0.0f)) z = 0.0f;
+    return z;
+}
+
+// ------------------------------------------------------------- sampling --
+
+struct Foot {
+    int xa, xb, ya, yb;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Foot footprint(float u, float v, int W, int H) {
+    Foot f;
+    float x = u * (float)W - 0.5f;
+    float y = v * (float)H - 0.5f;
+    if (!(fabsf(x) < 16777216.0f)) x = 0.0f;
+    if (!(fabsf(y) < 16777216.0f)) y = 0.0f;
+    float x0f = floorf(x), y0f = floorf(y);
+    f.fx = x - x0f;
+    f.fy = y - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    f.xa = ((x0 % W) + W) % W;
+    f.xb = (((x0 + 1) % W) + W) % W;
+    f.ya = y0 < 0 ? 0 : (y0 > H - 1 ? H - 1 : y0);
+    int y1 = y0 + 1;
+    f.yb = y1 < 0 ? 0 : (y1 > H - 1 ? H - 1 : y1);
+    return f;
+}
+
+// Bilinear sample of texture t of the perturbed scene (theta + sgn s eps).
+__device__ __forceinline__ void sample_tex(const DScene& sc, const float* __restrict__ th,
+                                           const uint32_t* __restrict__ pb, float e, float sgn, int t,
+                                           float u, float v, float* out) {
+    int W = sc.tex_w[t], H = sc.tex_h[t], C = sc.tex_c[t];
+    long long base = sc.tex_off[t];
+    Foot f = footprint(u, v, W, H);
+    float w00 = (1.0f - f.fx) * (1.0f - f.fy);
+    float w10 = f.fx * (1.0f - f.fy);
+    float w01 = (1.0f - f.fx) * f.fy;
+    float w11 = f.fx * f.fy;
+    long long i00 = base + ((long long)f.ya * W + f.xa) * C;
+    long long i10 = base + ((long long)f.ya * W + f.xb) * C;
+    long long i01 = base + ((long long)f.yb * W + f.xa) * C;
+    long long i11 = base + ((long long)f.yb * W + f.xb) * C;
+    for (int c = 0; c < C; ++c) {
+        float t00 = pval(th, i00 + c, e, pb, sgn);
+        float t10 = pval(th, i10 + c, e, pb, sgn);
+        float t01 = pval(th, i01 + c, e, pb, sgn);
+        float t11 = pval(th, i11 + c, e, pb, sgn);
+        out[c] = ((w00 * t00 + w10 * t10) + w01 * t01) + w11 * t11;
+    }
+}
+
+__device__ __forceinline__ void nrm3(float* x) {
+    float l2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
+    if (l2 > 0.0f) {
+        float inv = 1.0f / sqrtf(l2);
+        x[0] = x[0] * inv; x[1] = x[1] * inv; x[2] = x[2] * inv;
+    } else {
+        x[0] = 0.0f; x[1] = 0.0f; x[2] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ float dot3(const float* a, const float* b) {
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+__device__ __forceinline__ void cross3(const float* a, const float* b, float* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Colour and UV of pixel (px,py) (subpixel sample coordinates) covered by
+// triangle t: perspective-correct attributes, then unlit / Lambert / GGX.
+__device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, const float* __restrict__ th,
+                                            const uint32_t* __restrict__ pb, const float* eps, float sgn,
+                                            const TriR& r, const TriS& s, int t, int px, int py,
+                                            float* rgb, float* uvo) {
+    long long e0, e1, e2;
+    (void)inside(r, px, py, e0, e1, e2);
+    float fa = (float)r.area2;
+    float b0 = (float)e0 / fa, b1 = (float)e1 / fa, b2 = (float)e2 / fa;
+    float pc0 = b0 * s.iw[0], pc1 = b1 * s.iw[1], pc2 = b2 * s.iw[2];
+    float S = (pc0 + pc1) + pc2;
+    bool sw = (r.flags & TRI_SWAPPED) != 0u;
+    int o1 = sw ? 2 : 1, o2 = sw ? 1 : 2;
+    const float* cuv = sc.cuv + 6 * (long long)t;
+    float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];
+    float un1 = sw ? cu2 : cu1, vn1 = sw ? cv2 : cv1, un2 = sw ? cu1 : cu2, vn2 = sw ? cv1 : cv2;
+    float u = ((pc0 * cu0 + pc1 * un1) + pc2 * un2) / S;
+    float v = ((pc0 * cv0 + pc1 * vn1) + pc2 * vn2) / S;
+    uvo[0] = u;
+    uvo[1] = v;
+    float alb[3] = {0.0f, 0.0f, 0.0f};
+    if (sc.n_tex > 0) sample_tex(sc, th, pb, eps[1], sgn, 0, u, v, alb);
+    if (sc.shading == 0) {
+        rgb[0] = alb[0]; rgb[1] = alb[1]; rgb[2] = alb[2];
+        return;
+    }
+    float e1v[3], e2v[3], nf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { e1v[c] = s.p[3 + c] - s.p[c]; e2v[c] = s.p[6 + c] - s.p[c]; }
+    cross3(e1v, e2v, nf);
+    nrm3(nf);
+    if (sc.shading == 1) {
+        float ndl = dot3(nf, sc.light);
+        if (!(ndl > 0.0f)) ndl = 0.0f;
+        float sh = sc.ambient + sc.diffuse * ndl;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rgb[c] = alb[c] * (sh * sc.light_rgb[c]);
+        return;
+    }
+    // GGX with a tangent-space normal map in the face's UV frame
+    float du1 = cu1 - cu0, dv1 = cv1 - cv0, du2 = cu2 - cu0, dv2 = cv2 - cv0;
+    float rr = du1 * dv2 - du2 * dv1;
+    float T[3], B[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[c] = e1v[c] * dv2 - e2v[c] * dv1;
+    if (rr < 0.0f) { T[0] = -T[0]; T[1] = -T[1]; T[2] = -T[2]; }
+    float nt = dot3(nf, T);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[c] = T[c] - nf[c] * nt;
+    nrm3(T);
+    cross3(nf, T, B);
+    float nm[3] = {0.5f, 0.5f, 1.0f};
+    if (sc.n_tex > 1) sample_tex(sc, th, pb, eps[2], sgn, 1, u, v, nm);
+    float tn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tn[c] = 2.0f * nm[c] - 1.0f;
+    float n[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n[c] = (T[c] * tn[0] + B[c] * tn[1]) + nf[c] * tn[2];
+    nrm3(n);
+    float rough = 0.5f;
+    if (sc.n_tex > 2) sample_tex(sc, th, pb, eps[3], sgn, 2, u, v, &rough);
+    float P[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float q0 = s.p[c], q1 = s.p[3 * o1 + c], q2 = s.p[3 * o2 + c];
+        P[c] = ((pc0 * q0 + pc1 * q1) + pc2 * q2) / S;
+    }
+    float V[3] = {vw.cam[0] - P[0], vw.cam[1] - P[1], vw.cam[2] - P[2]};
+    nrm3(V);
+    const float* L = sc.light;
+    float Hh[3] = {L[0] + V[0], L[1] + V[1], L[2] + V[2]};
+    nrm3(Hh);
+    float ndl = dot3(n, L), ndv = dot3(n, V), ndh = dot3(n, Hh), vdh = dot3(V, Hh);
+    if (!(ndl > 0.0f)) ndl = 0.0f;
+    if (!(ndv > 0.0f)) ndv = 0.0f;
+    if (!(ndh > 0.0f)) ndh = 0.0f;
+    if (!(vdh > 0.0f)) vdh = 0.0f;
+    float alpha = rough * rough;
+    if (!(alpha > 0.002f)) alpha = 0.002f;
+    float a2 = alpha * alpha;
+    float dd = (ndh * ndh) * (a2 - 1.0f) + 1.0f;
+    float D = a2 / ((DRD_PI * dd) * dd);
+    float k = alpha * 0.5f;
+    float g1l = ndl / (ndl * (1.0f - k) + k);
+    float g1v = ndv / (ndv * (1.0f - k) + k);
+    float G = g1l * g1v;
+    float om = 1.0f - vdh;
+    float om5 = ((om * om) * (om * om)) * om;
+    float F = 0.04f + 0.96f * om5;
+    float spec = 0.0f;
+    if (ndl > 0.0f && ndv > 0.0f) spec = ((D * G) * F) / ((4.0f * ndl) * ndv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        rgb[c] = ((alb[c] * DRD_INV_PI + spec) * sc.light_rgb[c]) * ndl + sc.ambient * alb[c];
+}
+
+// Fixed-point code of a loss difference: round-half-even(delta * 2^32),
+// clamped to +-2^37; NaN gives 0.  flag: 1 saturated, 2 NaN.
+__device__ __forceinline__ long long quantize(float delta, int& flag) {
+    flag = 0;
+    if (delta != delta) { flag = 2; return 0; }
+    if (fabsf(delta) > 32.0f) {
+        flag = 1;
+        return delta > 0.0f ? (1ll << 37) : -(1ll << 37);
+    }
+    return (long long)rintf(delta * 4294967296.0f);
+}

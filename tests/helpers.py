@@ -81,3 +81,24 @@ def grid_scene(n, jitter, seed, z=0.0, lo=-0.9, hi=0.9, tex=None):
     if tex is None:
         tex = np.full((4, 4, 3), 0.5, np.float32)
     return SimpleScene(tri, corner_uv, P.astype(np.float32), [tex])
+
+
+def sphere_scene(freq, splits=0, res=(96, 80), shading=0, tex_shapes=((48, 48, 3),), seed=0, views=1,
+                 tex_mode=0, eps=None):
+    """A small seeded sphere scene (scenes.Scene) with arbitrary texture
+    shapes and view size, for parity cases that span several tiles."""
+    from paper_2404_09758_amd import scenes as S
+    rng = np.random.default_rng(seed)
+    v, f, uv = S._sphere_scene(freq, splits)
+    tex = [rng.uniform(0.05, 0.95, s).astype(np.float32) for s in tex_shapes]
+    ttex = [rng.uniform(0.05, 0.95, s).astype(np.float32) for s in tex_shapes]
+    tpos = S._radial_displace(v, seed + 7, amp=0.08).astype(np.float32)
+    W, Hh = res
+    vs = [S.look_at_view(W, Hh, 37.0 * k + 10.0, 15.0) for k in range(views)]
+    if eps is None:
+        fy = 1.0 / np.tan(np.radians(S.FOVY_DEG) / 2)
+        eps = [1.5 * (S.CAM_DIST / fy) * 2.0 / Hh] + [1.0 / 255.0] * len(tex_shapes)
+    return S.Scene("sphere", f.astype(np.int32), uv, v.astype(np.float32), tex, tpos, ttex, vs,
+                   shading=shading, tex_mode=tex_mode, ambient=0.1 if shading == 1 else 0.03,
+                   light_rgb=np.full(3, 1.0 if shading != 2 else 3.0, np.float32),
+                   eps=list(eps), lr=list(eps), n_pairs=1)

@@ -1,0 +1,268 @@
+"""GPU (HIP, gfx950) vs CPU oracle, element by element, through the C ABI.
+
+Bar: bit-exact on sign bits, triangle IDs, contribution counts K and the
+fixed-point sums Q; colours, UVs, decoded gradients and updated parameters
+are compared bit for bit as well (both sides evaluate the same fp32
+operation sequence), which is stricter than the 1e-5 relative tolerance the
+float outputs are allowed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2404_09758_amd import api
+from paper_2404_09758_amd import scenes as S
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def scene_by_name(name):
+    if name == "tiny":
+        return S.make_tiny()
+    if name == "octa":
+        return S.make_octa_small()
+    if name == "lambert":
+        return H.sphere_scene(6, 0, res=(96, 80), shading=S.SHADING_LAMBERT, tex_shapes=((48, 48, 3),),
+                              seed=1, views=2)
+    if name == "ggx":
+        return H.sphere_scene(5, 1, res=(100, 75), shading=S.SHADING_GGX,
+                              tex_shapes=((32, 32, 3), (32, 32, 3), (16, 16, 1)), seed=2, views=2)
+    if name == "nearest":
+        return H.sphere_scene(6, 0, res=(80, 64), shading=S.SHADING_UNLIT, tex_shapes=((40, 24, 3),),
+                              seed=3, views=1, tex_mode=S.TEX_NEAREST)
+    raise KeyError(name)
+
+
+def targets_of(o, sc):
+    th = sc.flat_params(True)
+    return [o.render(th, v)[0] for v in sc.views]
+
+
+# ------------------------------------------------------------------ signs --
+
+@pytest.mark.parametrize("n_verts", [1, 11, 86, 33334])
+def test_sign_bits_bit_exact(n_verts):
+    sc = H.SimpleScene(np.zeros((1, 3), np.int32), np.zeros((1, 3, 2), np.float32),
+                       np.zeros((n_verts, 3), np.float32), [])
+    sc.tri = np.array([[0, 0, 0]], np.int32)
+    ctx = api.Context(sc, DEV)
+    d = ctx.d
+    for (seed, step, pair, scene) in [(0, 0, 0, 0), (123456789012345, 7, 3, 2), (2 ** 64 - 1, 2 ** 32 - 1, 9, 1)]:
+        bits = host(ctx.signs(seed, step, pair, scene)).view(np.uint32)
+        got = np.where((bits[np.arange(d) >> 5] >> (np.arange(d) & 31).astype(np.uint32)) & 1, -1, 1)
+        ref = oracle.signs(seed, step, pair, scene, d)
+        assert np.array_equal(got.astype(np.int8), ref)
+
+
+# ----------------------------------------------------------------- render --
+
+@pytest.mark.parametrize("name", ["tiny", "octa", "lambert", "ggx", "nearest"])
+@pytest.mark.parametrize("tile,cap", [(8, 256), (16, 256), (32, 256), (16, 1)])
+def test_render_bit_exact(name, tile, cap):
+    sc = scene_by_name(name)
+    o = oracle.Oracle(sc)
+    ctx = api.Context(sc, DEV, tuning=(tile, cap, 1))
+    theta = sc.flat_params()
+    th = dev(theta)
+    seed, step, pair = 99, 4, 1
+    s = oracle.signs(seed, step, pair, 0, o.d)
+    for view in sc.views:
+        for sign in (None, +1, -1):
+            if sign is None:
+                rgb_o, id_o, uv_o = o.render(theta, view)
+                rgb, ids, uv = ctx.render(th, view)
+            else:
+                rgb_o, id_o, uv_o = o.render(theta, view, signs_=s, sign=sign, eps=sc.eps)
+                rgb, ids, uv = ctx.render(th, view, pert=dict(seed=seed, step=step, pair=pair, sign=sign,
+                                                              eps=sc.eps))
+            ids = host(ids).view(np.uint32)
+            assert np.array_equal(ids, id_o), f"ids differ at {np.argwhere(ids != id_o)[:5]}"
+            assert np.array_equal(host(uv), uv_o)
+            assert np.array_equal(host(rgb), rgb_o)
+            assert (id_o != oracle.BG_ID).sum() > 0
+
+
+# --------------------------------------------------------------- estimate --
+
+CASES = [
+    # name, pairs, tuning, eps override
+    ("tiny", 1, (16, 256, 1), None),
+    ("tiny", 3, (8, 256, 0), None),
+    ("octa", 6, (8, 1, 1), None),            # every bin overflows: fallback path
+    ("lambert", 3, (32, 256, 0), None),
+    ("lambert", 2, (16, 4, 1), [0.0, 1.0 / 255.0]),   # frozen positions, some overflow
+    ("ggx", 2, (16, 256, 0), None),
+    ("ggx", 1, (8, 64, 1), [0.01, 0.0, 1.0 / 255.0, 0.0]),  # frozen albedo and roughness
+    ("nearest", 2, (16, 256, 1), None),
+]
+
+
+@pytest.mark.parametrize("name,pairs,tuning,eps", CASES)
+def test_estimate_Q_K_bit_exact(name, pairs, tuning, eps):
+    sc = scene_by_name(name)
+    eps = sc.eps if eps is None else eps
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    seed, step = 2024, 3
+    Qo, Ko, _, st = o.estimate(theta, sc.views, tg, seed, step, pairs, eps)
+    ctx = api.Context(sc, DEV, tuning=tuning)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], seed, step, pairs, eps)
+    Qg, Kg = host(Q), host(K).view(np.uint32)
+    assert np.array_equal(Kg, Ko), f"K differs at {np.nonzero(Kg != Ko)[0][:10]}"
+    assert np.array_equal(Qg, Qo), f"Q differs at {np.nonzero(Qg != Qo)[0][:10]}"
+    assert Ko.sum() > 0 and np.count_nonzero(Qo) > 0
+    gs = ctx.stats()
+    assert gs["saturations"] == st["saturations"] and gs["nonfinite"] == st["nonfinite"]
+    if tuning[1] == 1:
+        assert gs["tile_overflows"] > 0
+
+
+def test_estimate_accumulates_and_plain_equals_batched():
+    sc = scene_by_name("lambert")
+    o = oracle.Oracle(sc)
+    tg = [dev(t) for t in targets_of(o, sc)]
+    th = dev(sc.flat_params())
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 1))
+    Q1, K1 = ctx.estimate_grad(th, sc.views, tg, 5, 1, 4, sc.eps)
+    ctx.set_tuning(32, 16, 0)
+    Q2, K2 = ctx.estimate_grad(th, sc.views, tg, 5, 1, 4, sc.eps)
+    assert torch.equal(Q1, Q2) and torch.equal(K1, K2)
+    # accumulating two calls = one call over the union of the work
+    Qa, Ka = ctx.estimate_grad(th, sc.views[:1], tg[:1], 5, 1, 4, sc.eps)
+    Qa, Ka = ctx.estimate_grad(th, sc.views[1:], tg[1:], 5, 1, 4, sc.eps, Q=Qa, K=Ka)
+    assert torch.equal(Qa, Q1) and torch.equal(Ka, K1)
+
+
+# ---------------------------------------------------------- decode / step --
+
+@pytest.mark.parametrize("kind,averaging", [(S.OPT_ADAM, S.AVG_COUNT), (S.OPT_SGD, S.AVG_COUNT),
+                                            (S.OPT_ADAM, S.AVG_PAIRS)])
+def test_decode_and_step_bit_exact(kind, averaging):
+    sc = scene_by_name("ggx")
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    pairs = 2
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 77, 1, pairs, sc.eps)
+    ctx = api.Context(sc, DEV)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 77, 1, pairs, sc.eps)
+    g = host(ctx.decode_grad(Q, K, sc.eps, averaging, pairs))
+    assert np.array_equal(g, o.decode(Qo, Ko, sc.eps, averaging, pairs))
+    lr = [1e-3, 2e-3, 3e-3, 4e-3]
+    rng = np.random.default_rng(0)
+    m0 = rng.normal(0, 1e-3, o.d).astype(np.float32)
+    v0 = rng.uniform(0, 1e-5, o.d).astype(np.float32)
+    th, m, v = dev(theta), dev(m0), dev(v0)
+    ctx.step(th, m, v, 3, Q, K, sc.eps, pairs, kind=kind, averaging=averaging, lr=lr)
+    tho, mo, vo = theta.copy(), m0.copy(), v0.copy()
+    o.step(tho, mo, vo, 3, Qo, Ko, sc.eps, pairs, kind=kind, averaging=averaging, lr=lr)
+    assert np.array_equal(host(th), tho)
+    assert np.array_equal(host(m), mo) and np.array_equal(host(v), vo)
+    assert int(host(Q).any()) == 0 and int(host(K).any()) == 0
+
+
+def test_tiny_sgd_trajectory_bit_exact():
+    """Five estimate + SGD steps on both sides stay identical."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta_o = sc.flat_params().copy()
+    mo = np.zeros_like(theta_o)
+    vo = np.zeros_like(theta_o)
+    ctx = api.Context(sc, DEV)
+    th = dev(theta_o)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    tgd = [dev(t) for t in tg]
+    for t in range(1, 6):
+        Qo, Ko, _, _ = o.estimate(theta_o, sc.views, tg, 31, t, 1, sc.eps)
+        o.step(theta_o, mo, vo, t, Qo, Ko, sc.eps, 1, kind=S.OPT_SGD, averaging=S.AVG_COUNT, lr=sc.lr)
+        Q, K = ctx.estimate_grad(th, sc.views, tgd, 31, t, 1, sc.eps)
+        ctx.step(th, m, v, t, Q, K, sc.eps, 1, kind=S.OPT_SGD, averaging=S.AVG_COUNT, lr=sc.lr)
+        assert np.array_equal(host(th), theta_o), f"diverged at step {t}"
+
+
+# ------------------------------------------------------------- edge cases --
+
+def test_empty_view_and_single_pixel():
+    sc = scene_by_name("lambert")
+    o = oracle.Oracle(sc)
+    ctx = api.Context(sc, DEV)
+    theta = sc.flat_params()
+    away = S.View(64, 48, S.look_at_view(64, 48, 0.0, 0.0).view_proj.copy(),
+                  np.array([0, 0, 3], np.float32))
+    away.view_proj[0, :] = 0.0
+    away.view_proj[0, 3] = 5.0      # every vertex maps far to the right of the screen
+    rgb, ids, _ = ctx.render(dev(theta), away)
+    assert np.all(host(ids).view(np.uint32) == oracle.BG_ID) and float(host(rgb).sum()) == 0.0
+    tg = np.zeros((48, 64, 3), np.float32)
+    Q, K = ctx.estimate_grad(dev(theta), [away], [dev(tg)], 1, 1, 2, sc.eps)
+    assert not host(Q).any() and not host(K).any()
+    one = S.look_at_view(1, 1, 0.0, 0.0)
+    rgb_o, id_o, uv_o = o.render(theta, one)
+    rgb, ids, uv = ctx.render(dev(theta), one)
+    assert np.array_equal(host(ids).view(np.uint32), id_o) and np.array_equal(host(rgb), rgb_o)
+
+
+def test_views_of_different_sizes_in_one_call():
+    sc = scene_by_name("octa")
+    sc.views = [S.look_at_view(16, 16, 30.0, 15.0), S.look_at_view(23, 17, 200.0, -20.0),
+                S.look_at_view(40, 9, 90.0, 60.0)]
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 8, 2, 5, sc.eps)
+    for tuning in [(8, 256, 1), (16, 2, 0)]:
+        ctx = api.Context(sc, DEV, tuning=tuning)
+        Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 8, 2, 5, sc.eps)
+        assert np.array_equal(host(Q), Qo) and np.array_equal(host(K).view(np.uint32), Ko)
+
+
+def test_invalid_arguments_raise():
+    sc = scene_by_name("tiny")
+    ctx = api.Context(sc, DEV)
+    th = dev(sc.flat_params())
+    with pytest.raises(api.DRError):
+        ctx.estimate_grad(th, sc.views, [torch.zeros(64 * 64 * 3, device=DEV)], 1, 1, 0, sc.eps)
+    with pytest.raises(api.DRError):
+        ctx.estimate_grad(th, sc.views, [torch.zeros(64 * 64 * 3, device=DEV)], 1, 1, 1, [-1.0, 0.1])
+    with pytest.raises(api.DRError):
+        ctx.set_tuning(12, 256, 1)
+    bad = S.make_tiny()
+    bad.tri = bad.tri.copy()
+    bad.tri[5, 1] = bad.pos.shape[0]         # out-of-range vertex index
+    with pytest.raises(api.DRError):
+        api.Context(bad, DEV)
+
+
+# ------------------------------------------------------- full-size samples --
+
+@pytest.mark.parametrize("name", ["mid", "paper"])
+def test_full_size_one_pair_one_view_bit_exact(name):
+    """At full configuration size (512^2 / 1024^2, 20K / 46K triangles, the
+    bench's tiling), one (pair, view) of the estimator matches the oracle."""
+    sc = S.CONFIGS[name]()
+    sc.views = sc.views[:1]
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 11, 1, 1, sc.eps)
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 11, 1, 1, sc.eps)
+    assert np.array_equal(host(K).view(np.uint32), Ko)
+    assert np.array_equal(host(Q), Qo)
+    rgb_o, id_o, _ = o.render(theta, sc.views[0])
+    rgb, ids, _ = ctx.render(dev(theta), sc.views[0])
+    assert np.array_equal(host(ids).view(np.uint32), id_o) and np.array_equal(host(rgb), rgb_o)

@@ -189,6 +189,10 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
         d += (long long)s->tex_w[t] * s->tex_h[t] * s->tex_c[t];
     }
     if (d >= (1ll << 36)) return DR_E_INVALID;
+    // group indices are 32-bit keys in the tile-local aggregation tables
+    long long groups = s->n_verts;
+    for (int t = 0; t < s->n_tex; ++t) groups += (long long)s->tex_w[t] * s->tex_h[t];
+    if (groups >= 0xFFFFFFFFll) return DR_E_UNSUPPORTED;
     dr_ctx* c = new (std::nothrow) dr_ctx();
     if (!c) return DR_E_OOM;
     c->hs = *s;

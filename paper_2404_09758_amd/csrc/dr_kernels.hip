@@ -165,11 +165,81 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
     }
 }
 
-__device__ __forceinline__ void scatter_one(long long* __restrict__ Rp, unsigned* __restrict__ K,
-                                            long long g, long long q) {
+// ------------------------------------------------ tile-local aggregation --
+//
+// Contributions are summed per group inside the workgroup before they reach
+// the global accumulators: an open-addressing table in LDS keyed by group
+// (int64 sum + uint32 count per slot), flushed with one global atomic pair
+// per distinct group of the tile.  Integer sums make the result identical
+// to per-pixel global atomics.
+
+#define HASH_EMPTY 0xFFFFFFFFu
+#define HASH_PROBES 64
+
+template <int LOG2T>
+struct GroupTable {
+    unsigned key[1 << LOG2T];
+    unsigned long long sum[1 << LOG2T];
+    unsigned cnt[1 << LOG2T];
+};
+
+__device__ __forceinline__ void global_add(long long* __restrict__ Rp, unsigned* __restrict__ K, long long g,
+                                           long long q, unsigned c) {
     if (q != 0) atomicAdd((unsigned long long*)&Rp[g], (unsigned long long)q);
-    atomicAdd(&K[g], 1u);
+    atomicAdd(&K[g], c);
 }
+
+template <int LOG2T>
+__device__ __forceinline__ void table_add(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
+                                          unsigned* __restrict__ K, unsigned g, long long q, unsigned c) {
+    constexpr unsigned MASK = (1u << LOG2T) - 1u;
+    unsigned h = (g * 2654435761u) >> (32 - LOG2T);
+    for (int probe = 0; probe < HASH_PROBES; ++probe) {
+        unsigned k = __hip_atomic_load(&tb.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == HASH_EMPTY) k = atomicCAS(&tb.key[h], HASH_EMPTY, g);
+        if (k == HASH_EMPTY || k == g) {
+            if (q != 0) atomicAdd(&tb.sum[h], (unsigned long long)q);
+            atomicAdd(&tb.cnt[h], c);
+            return;
+        }
+        h = (h + 1u) & MASK;
+    }
+    global_add(Rp, K, g, q, c);      // crowded table: go straight to memory
+}
+
+// Wave-level combine of the vertex contributions of pixels whose + and -
+// renders show the same triangle: lanes with equal triangle ids are summed
+// with a butterfly and one lane adds the three vertices.  Must be called by
+// every lane of the wave.
+template <int LOG2T>
+__device__ __forceinline__ void wave_vertices(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
+                                              unsigned* __restrict__ K, bool active, unsigned tri,
+                                              int v0, int v1, int v2, long long q) {
+    int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        int leader = __ffsll((unsigned long long)pending) - 1;
+        unsigned lt = __shfl(tri, leader);
+        bool mine = active && tri == lt;
+        unsigned long long m = __ballot(mine);
+        long long v = mine ? q : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == leader) {
+            unsigned c = (unsigned)__popcll(m);
+            table_add<LOG2T>(tb, Rp, K, (unsigned)v0, v, c);
+            table_add<LOG2T>(tb, Rp, K, (unsigned)v1, v, c);
+            table_add<LOG2T>(tb, Rp, K, (unsigned)v2, v, c);
+        }
+        if (mine) active = false;
+        pending &= ~m;
+    }
+}
+
+template <int TILE>
+struct TileCfg {
+    static constexpr int LOG2T = TILE == 8 ? 9 : (TILE == 16 ? 10 : 11);
+};
 
 template <int TILE, bool RENDER>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile(TileArgs a) {
@@ -178,6 +248,8 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     constexpr int TB = NPIX / PPT;
     constexpr int NW = TB / 64;
     constexpr int NS = RENDER ? 1 : 2;
+    constexpr int LOG2T = TileCfg<TILE>::LOG2T;
+    constexpr int TSIZE = 1 << LOG2T;
     __shared__ unsigned long long key[NS][NPIX];
 
     const DScene& sc = a.sc;
@@ -193,6 +265,14 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int j = tid; j < NS * NPIX; j += TB) (&key[0][0])[j] = ~0ull;
+    __shared__ GroupTable<RENDER ? 1 : LOG2T> table;
+    if constexpr (!RENDER) {
+        for (int j = tid; j < TSIZE; j += TB) {
+            table.key[j] = HASH_EMPTY;
+            table.sum[j] = 0ull;
+            table.cnt[j] = 0u;
+        }
+    }
     __syncthreads();
 
     unsigned cnt[NS];
@@ -229,18 +309,19 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     }
 
     const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
+    long long* Rp = RENDER ? nullptr : a.R + (long long)pair * sc.G;
     for (int j = 0; j < PPT; ++j) {
         int local = tid + j * TB;
         int lx = local % TILE, ly = local / TILE;
         int x = px0 + lx, y = py0 + ly;
-        if (x >= vw.W || y >= vw.H) continue;
+        bool inpix = x < vw.W && y < vw.H;
         int px = 256 * x + 128, py = 256 * y + 128;
         unsigned id[NS];
         float rgb[NS][3], uv[NS][2];
         int vids[NS][3];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            unsigned long long k = key[s][local];
+            unsigned long long k = inpix ? key[s][local] : ~0ull;
             id[s] = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
             rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
             uv[s][0] = 0.0f; uv[s][1] = 0.0f;
@@ -255,6 +336,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
         }
         long long pix = (long long)y * vw.W + x;
         if constexpr (RENDER) {
+            if (!inpix) continue;
             if (a.out_rgb) {
                 a.out_rgb[3 * pix + 0] = rgb[0][0];
                 a.out_rgb[3 * pix + 1] = rgb[0][1];
@@ -266,71 +348,88 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
                 a.out_uv[2 * pix + 1] = uv[0][1];
             }
         } else {
-            if ((id[0] == DRD_BG && id[1] == DRD_BG) || !a.any_act) continue;   // empty contribution set
-            const float* tg = a.targets + vw.tgt_off + 3 * pix;
-            float t0 = tg[0], t1 = tg[1], t2 = tg[2];
-            float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
-            float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
-            float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
-            float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
-            int flag;
-            long long q = quantize(fp - fm, flag);
-            if (flag) atomicAdd(&a.stats[flag], 1ull);
-            long long* Rp = a.R + (long long)pair * sc.G;
+            // an empty contribution set (background in both renders) adds nothing
+            bool act = inpix && (id[0] != DRD_BG || id[1] != DRD_BG) && a.any_act;
+            long long q = 0;
+            if (act) {
+                const float* tg = a.targets + vw.tgt_off + 3 * pix;
+                float t0 = tg[0], t1 = tg[1], t2 = tg[2];
+                float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
+                float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
+                float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
+                float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
+                int flag;
+                q = quantize(fp - fm, flag);
+                if (flag) atomicAdd(&a.stats[flag], 1ull);
+            }
             if (a.act_pos) {
-                if (id[0] != DRD_BG) {
-                    scatter_one(Rp, a.K, vids[0][0], q);
-                    scatter_one(Rp, a.K, vids[0][1], q);
-                    scatter_one(Rp, a.K, vids[0][2], q);
-                }
-                if (id[1] != DRD_BG) {
+                // same triangle in both renders: combined per wave
+                bool same = act && id[0] == id[1];
+                wave_vertices<LOG2T>(table, Rp, a.K, same, id[0], vids[0][0], vids[0][1], vids[0][2], q);
+                if (act && !same) {
+                    // the union of the two triangles' vertices, each once
+                    if (id[0] != DRD_BG) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        int g = vids[1][k];
-                        bool dup = (g == vids[0][0]) || (g == vids[0][1]) || (g == vids[0][2]);
-                        if (!dup) scatter_one(Rp, a.K, g, q);
+                        for (int k = 0; k < 3; ++k) table_add<LOG2T>(table, Rp, a.K, (unsigned)vids[0][k], q, 1u);
+                    }
+                    if (id[1] != DRD_BG) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            int g = vids[1][k];
+                            bool dup = (g == vids[0][0]) || (g == vids[0][1]) || (g == vids[0][2]);
+                            if (!dup) table_add<LOG2T>(table, Rp, a.K, (unsigned)g, q, 1u);
+                        }
                     }
                 }
             }
-            for (int c = 0; c < sc.n_cls; ++c) {
-                if (!a.act_cls[c]) continue;
-                int W = sc.cls_w[c], H = sc.cls_h[c];
-                long long base = sc.cls_goff[c];
-                long long gs[NS][4];
+            if (act) {
+                for (int c = 0; c < sc.n_cls; ++c) {
+                    if (!a.act_cls[c]) continue;
+                    int W = sc.cls_w[c], H = sc.cls_h[c];
+                    long long base = sc.cls_goff[c];
+                    long long gs[NS][4];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    gs[s][0] = gs[s][1] = gs[s][2] = gs[s][3] = -1;
-                    if (id[s] == DRD_BG) continue;
-                    Foot f = footprint(uv[s][0], uv[s][1], W, H);
-                    if (sc.tex_mode == 1) {
-                        int xn = (f.fx >= 0.5f) ? f.xb : f.xa;
-                        int yn = (f.fy >= 0.5f) ? f.yb : f.ya;
-                        gs[s][0] = base + (long long)yn * W + xn;
-                    } else {
-                        gs[s][0] = base + (long long)f.ya * W + f.xa;
-                        gs[s][1] = base + (long long)f.ya * W + f.xb;
-                        gs[s][2] = base + (long long)f.yb * W + f.xa;
-                        gs[s][3] = base + (long long)f.yb * W + f.xb;
+                    for (int s = 0; s < NS; ++s) {
+                        gs[s][0] = gs[s][1] = gs[s][2] = gs[s][3] = -1;
+                        if (id[s] == DRD_BG) continue;
+                        Foot f = footprint(uv[s][0], uv[s][1], W, H);
+                        if (sc.tex_mode == 1) {
+                            int xn = (f.fx >= 0.5f) ? f.xb : f.xa;
+                            int yn = (f.fy >= 0.5f) ? f.yb : f.ya;
+                            gs[s][0] = base + (long long)yn * W + xn;
+                        } else {
+                            gs[s][0] = base + (long long)f.ya * W + f.xa;
+                            gs[s][1] = base + (long long)f.ya * W + f.xb;
+                            gs[s][2] = base + (long long)f.yb * W + f.xa;
+                            gs[s][3] = base + (long long)f.yb * W + f.xb;
+                        }
                     }
-                }
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
+                    for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        long long g = gs[s][k];
-                        if (g < 0) continue;
-                        bool dup = false;
-#pragma unroll
-                        for (int j2 = 0; j2 < 4; ++j2)
-                            if (j2 < k && gs[s][j2] == g) dup = true;
-                        if (s == 1) {
+                        for (int k = 0; k < 4; ++k) {
+                            long long g = gs[s][k];
+                            if (g < 0) continue;
+                            bool dup = false;
 #pragma unroll
                             for (int j2 = 0; j2 < 4; ++j2)
-                                if (gs[0][j2] == g) dup = true;
+                                if (j2 < k && gs[s][j2] == g) dup = true;
+                            if (s == 1) {
+#pragma unroll
+                                for (int j2 = 0; j2 < 4; ++j2)
+                                    if (gs[0][j2] == g) dup = true;
+                            }
+                            if (!dup) table_add<LOG2T>(table, Rp, a.K, (unsigned)g, q, 1u);
                         }
-                        if (!dup) scatter_one(Rp, a.K, g, q);
-                    }
+                }
             }
+        }
+    }
+    if constexpr (!RENDER) {
+        __syncthreads();
+        for (int j = tid; j < TSIZE; j += TB) {
+            unsigned g = table.key[j];
+            if (g != HASH_EMPTY) global_add(Rp, a.K, (long long)g, (long long)table.sum[j], table.cnt[j]);
         }
     }
 }

@@ -24,11 +24,26 @@ METRIC = "optimisation steps/s at 1024², 50K tris (batched vs plain); % of HBM 
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes of the fused raster/shade/loss/scatter kernel (k_tile):
-# per pixel-estimate the target pixel is read once (12 B: the only per-pixel
-# HBM input once the + and - renders stay on chip), and every contribution
-# (pixel-estimate, group) adds one int64 sum and one uint32 count (12 B).
+# per pixel-estimate the target pixel is read once (12 B), the only per-pixel
+# HBM input once the + and - renders stay on chip.
 BYTES_PER_PIXEL_ESTIMATE = 12
-BYTES_PER_CONTRIBUTION = 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per k_tile launch from the committed rocprofv3 counters, or
+    None when the kernel sources changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["kernel_sources_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def parse():
@@ -40,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="both", choices=["both", "batched", "plain"])
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="after the run, copy a float32 buffer of this many MiB 3 times (a kernel of "
+                         "known traffic, to calibrate profiler byte counters)")
     return ap.parse_args()
 
 
@@ -143,8 +161,8 @@ def main():
     tm = r["timing"]
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     launches_per_step = tm["tile_launches"] / args.steps
-    alg_bytes_launch = (BYTES_PER_PIXEL_ESTIMATE * px_per_step
-                        + BYTES_PER_CONTRIBUTION * r["contributions_per_step"]) / launches_per_step
+    alg_bytes_launch = BYTES_PER_PIXEL_ESTIMATE * px_per_step / launches_per_step
+    traffic = measured_traffic() if main_mode == "batched" and args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -165,14 +183,23 @@ def main():
                    "mode": main_mode, "tile_px": 16, "bin_capacity": 256,
                    "pixel_estimates_per_step": px_per_step},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_tile", "kernel_avg_ms": tile_avg_ms,
                      "alg_bytes_per_launch": alg_bytes_launch},
+        "contributions_per_step": r["contributions_per_step"],
         "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")},
         "pixel_estimates_per_s": px_per_step * 1e3 / r["ms_per_step"],
     }
     for name, rr in results.items():
         out[f"{name}_steps_per_s"] = 1e3 / rr["ms_per_step"]
+    if args.probe_copy_mib > 0:
+        n = args.probe_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 4 * n
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_items)
     print(json.dumps(out), flush=True)

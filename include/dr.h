@@ -139,6 +139,13 @@ int64_t dr_group_count(const dr_ctx* ctx);       /* number of groups G        */
 dr_status dr_render(dr_ctx* ctx, const float* theta, const dr_view* view, const dr_perturb* pert,
                     float* rgb, uint32_t* id, float* uv);
 
+/* The objective of Table 1: f(theta) = || I(theta) - I ||^2 = sum over
+ * pixels of f_{w,h}, per view.  targets as for dr_estimate_grad; loss
+ * [n_views] double (device), each the sum of the per-pixel fp32 errors in
+ * a fixed order (reproducible run to run). */
+dr_status dr_loss(dr_ctx* ctx, const float* theta, const dr_view* views, int32_t n_views,
+                  const float* targets, double* loss);
+
 /* The sign vector of one pair (Alg. 1, randomsign): bit i of the uint32
  * words bits[ceil(d/32)] set means s_i = -1. */
 dr_status dr_signs(dr_ctx* ctx, uint64_t seed, uint32_t step, uint32_t pair, uint32_t scene_index,

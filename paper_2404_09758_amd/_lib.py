@@ -68,6 +68,7 @@ SIGNATURES = {
     "dr_param_count": (C.c_int64, [_vp]),
     "dr_group_count": (C.c_int64, [_vp]),
     "dr_render": (C.c_int, [_vp, _vp, C.POINTER(View), C.POINTER(Perturb), _vp, _vp, _vp]),
+    "dr_loss": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, _vp]),
     "dr_signs": (C.c_int, [_vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "dr_estimate_grad": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
                                    C.c_int32, C.POINTER(C.c_float), _vp, _vp]),

@@ -152,6 +152,18 @@ class Context:
                    C.c_void_p(out_uv.data_ptr() if uv else 0))
         return out_rgb, out_id, out_uv
 
+    def loss(self, theta, views: Sequence, targets):
+        """Per-view L2 image error (float64 tensor [n_views])."""
+        dp = _check_tensor(theta, torch.float32, self.device, self.d, "theta")
+        if isinstance(targets, (list, tuple)):
+            targets = torch.cat([t.reshape(-1) for t in targets])
+        need = sum(3 * int(v.width) * int(v.height) for v in views)
+        dt = _check_tensor(targets, torch.float32, self.device, need, "targets")
+        out = torch.empty(len(views), dtype=torch.float64, device=self.device)
+        vws = (L.View * len(views))(*[make_view(v) for v in views])
+        self._call("dr_loss", C.c_void_p(dp), vws, len(views), C.c_void_p(dt), C.c_void_p(out.data_ptr()))
+        return out
+
     def signs(self, seed, step, pair, scene_index=0):
         words = (self.d + 31) // 32
         bits = torch.empty(words, dtype=torch.int32, device=self.device)

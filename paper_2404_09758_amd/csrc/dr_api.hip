@@ -33,6 +33,8 @@ struct dr_ctx {
     long long R_pairs = 0;
     uint32_t* bits = nullptr;
     long long bits_pairs = 0;
+    double* partials = nullptr;
+    long long partial_slots = 0;
     unsigned long long* stats = nullptr;
     // timing: event pairs recorded around launches while enabled
     bool timing = false;
@@ -278,7 +280,7 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
 extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats};
+    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats, c->partials};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < 5; ++k)
@@ -404,7 +406,7 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     ta.out_rgb = rgb;
     ta.out_id = id;
     ta.out_uv = uv;
-    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, true, 1, max_tiles); }));
+    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 1, 1, max_tiles); }));
     return DR_OK;
 }
 
@@ -497,7 +499,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
         sa.item0 = (int)i0;
         ta.item0 = (int)i0;
         HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
-        HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, false, n, max_tiles); }));
+        HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 0, n, max_tiles); }));
     }
     FoldArgs fa;
     std::memset(&fa, 0, sizeof(fa));
@@ -508,6 +510,76 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     for (int b = 0; b <= DRD_MAX_TEX; ++b) fa.eps[b] = dp.eps[b];
     fa.Q = (long long*)Q;
     HIPCHK(c, timed(c, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    return DR_OK;
+}
+
+// --------------------------------------------------------------- loss --
+
+extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                             const float* targets, double* loss) {
+    if (!c) return DR_E_INVALID;
+    if (!theta || !targets || !loss || !views) return fail(c, DR_E_INVALID, "NULL array argument");
+    if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
+    int tile = c->tune.tile_px;
+    DViews dv;
+    std::memset(&dv, 0, sizeof(dv));
+    long long tgt_off = 0;
+    int max_tiles = 1;
+    for (int v = 0; v < n_views; ++v) {
+        dr_status s = check_view(c, &views[v], tile);
+        if (s) return s;
+        dv.v[v] = make_dview(views[v], tile, tgt_off);
+        tgt_off += 3ll * views[v].width * views[v].height;
+        max_tiles = std::max(max_tiles, dv.v[v].tiles_x * dv.v[v].tiles_y);
+    }
+    dr_status s = device_guard(c);
+    if (s) return s;
+    s = ensure_raster(c, n_views, max_tiles);
+    if (s) return s;
+    s = grow(c, &c->partials, &c->partial_slots, (long long)n_views * max_tiles, sizeof(double), false);
+    if (s) return s;
+    DPert dp;
+    dp.bits = nullptr;
+    for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = 0.0f;
+    SetupArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.sc = c->sc;
+    sa.views = dv;
+    sa.pert = dp;
+    sa.theta = theta;
+    sa.n_views = n_views;
+    sa.item0 = 0;
+    sa.nsign = 1;
+    sa.sgn[0] = sa.sgn[1] = 1.0f;
+    sa.tile = tile;
+    sa.cap = c->tune.bin_capacity;
+    sa.max_tiles = max_tiles;
+    sa.recR = c->recR;
+    sa.recS = c->recS;
+    sa.counts = c->counts;
+    sa.bins = c->bins;
+    HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, n_views); }));
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.sc = c->sc;
+    ta.views = dv;
+    ta.pert = dp;
+    ta.theta = theta;
+    ta.n_views = n_views;
+    ta.item0 = 0;
+    ta.nsign = 1;
+    ta.sgn[0] = ta.sgn[1] = 1.0f;
+    ta.cap = c->tune.bin_capacity;
+    ta.max_tiles = max_tiles;
+    ta.recR = c->recR;
+    ta.recS = c->recS;
+    ta.counts = c->counts;
+    ta.bins = c->bins;
+    ta.stats = c->stats;
+    ta.targets = targets;
+    ta.partials = c->partials;
+    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 2, n_views, max_tiles); }));
+    HIPCHK(c, launch_sum_tiles(c->stream, c->partials, max_tiles, dv, n_views, loss));
     return DR_OK;
 }
 

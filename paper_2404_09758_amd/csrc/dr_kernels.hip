@@ -241,8 +241,11 @@ struct TileCfg {
     static constexpr int LOG2T = TILE == 8 ? 9 : (TILE == 16 ? 10 : 11);
 };
 
-template <int TILE, bool RENDER>
+// MODE: 0 estimate (both signs, scatter), 1 render (write rgb/id/uv),
+// 2 loss (per-tile sum of the per-pixel L2 error f_{w,h}).
+template <int TILE, int MODE>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile(TileArgs a) {
+    constexpr bool RENDER = MODE != 0;
     constexpr int NPIX = TILE * TILE;
     constexpr int PPT = NPIX > 256 ? NPIX / 256 : 1;
     constexpr int TB = NPIX / PPT;
@@ -310,6 +313,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
 
     const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
     long long* Rp = RENDER ? nullptr : a.R + (long long)pair * sc.G;
+    double loss_acc = 0.0;
     for (int j = 0; j < PPT; ++j) {
         int local = tid + j * TB;
         int lx = local % TILE, ly = local / TILE;
@@ -335,7 +339,13 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
             }
         }
         long long pix = (long long)y * vw.W + x;
-        if constexpr (RENDER) {
+        if constexpr (MODE == 2) {
+            if (inpix) {
+                const float* tg = a.targets + vw.tgt_off + 3 * pix;
+                float dr = rgb[0][0] - tg[0], dg = rgb[0][1] - tg[1], db = rgb[0][2] - tg[2];
+                loss_acc += (double)((dr * dr + dg * dg) + db * db);
+            }
+        } else if constexpr (MODE == 1) {
             if (!inpix) continue;
             if (a.out_rgb) {
                 a.out_rgb[3 * pix + 0] = rgb[0][0];
@@ -425,6 +435,17 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
             }
         }
     }
+    if constexpr (MODE == 2) {
+        // fixed-order tree reduction of the tile's per-pixel errors
+        __shared__ double red[TB];
+        red[tid] = loss_acc;
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if (tid < w) red[tid] = red[tid] + red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) a.partials[(long long)li * a.max_tiles + tile] = red[0];
+    }
     if constexpr (!RENDER) {
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
@@ -434,12 +455,33 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     }
 }
 
-template __global__ void k_tile<8, false>(TileArgs);
-template __global__ void k_tile<16, false>(TileArgs);
-template __global__ void k_tile<32, false>(TileArgs);
-template __global__ void k_tile<8, true>(TileArgs);
-template __global__ void k_tile<16, true>(TileArgs);
-template __global__ void k_tile<32, true>(TileArgs);
+template __global__ void k_tile<8, 0>(TileArgs);
+template __global__ void k_tile<16, 0>(TileArgs);
+template __global__ void k_tile<32, 0>(TileArgs);
+template __global__ void k_tile<8, 1>(TileArgs);
+template __global__ void k_tile<16, 1>(TileArgs);
+template __global__ void k_tile<32, 1>(TileArgs);
+template __global__ void k_tile<8, 2>(TileArgs);
+template __global__ void k_tile<16, 2>(TileArgs);
+template __global__ void k_tile<32, 2>(TileArgs);
+
+// Per-view loss: the tiles' partial sums added in tile order (one block per
+// view, fixed-order reduction), so the value is reproducible run to run.
+__global__ void __launch_bounds__(256) k_sum_tiles(const double* __restrict__ partials, int max_tiles,
+                                                   DViews views, double* __restrict__ out) {
+    __shared__ double red[256];
+    int v = blockIdx.x, tid = threadIdx.x;
+    int n = views.v[v].tiles_x * views.v[v].tiles_y;
+    double acc = 0.0;
+    for (int t = tid; t < n; t += 256) acc += partials[(long long)v * max_tiles + t];
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = red[tid] + red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[v] = red[0];
+}
 
 // ------------------------------------------------------------- k_fold --
 
@@ -550,19 +592,25 @@ hipError_t launch_setup(hipStream_t st, const SetupArgs& a, int n_items) {
     return hipGetLastError();
 }
 
-hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, bool render, int n_items, int max_tiles) {
+template <int TILE>
+static void launch_tile_t(hipStream_t st, const TileArgs& a, int mode, dim3 grid) {
+    dim3 block((TILE * TILE > 256) ? 256 : TILE * TILE);
+    if (mode == 0) hipLaunchKernelGGL((k_tile<TILE, 0>), grid, block, 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_tile<TILE, 1>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tile<TILE, 2>), grid, block, 0, st, a);
+}
+
+hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, int n_items, int max_tiles) {
     dim3 grid((unsigned)max_tiles, (unsigned)n_items);
-    int tb = (tile * tile > 256) ? 256 : tile * tile;
-    if (tile == 8) {
-        if (render) hipLaunchKernelGGL((k_tile<8, true>), grid, dim3(tb), 0, st, a);
-        else hipLaunchKernelGGL((k_tile<8, false>), grid, dim3(tb), 0, st, a);
-    } else if (tile == 16) {
-        if (render) hipLaunchKernelGGL((k_tile<16, true>), grid, dim3(tb), 0, st, a);
-        else hipLaunchKernelGGL((k_tile<16, false>), grid, dim3(tb), 0, st, a);
-    } else {
-        if (render) hipLaunchKernelGGL((k_tile<32, true>), grid, dim3(tb), 0, st, a);
-        else hipLaunchKernelGGL((k_tile<32, false>), grid, dim3(tb), 0, st, a);
-    }
+    if (tile == 8) launch_tile_t<8>(st, a, mode, grid);
+    else if (tile == 16) launch_tile_t<16>(st, a, mode, grid);
+    else launch_tile_t<32>(st, a, mode, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tiles, const DViews& views,
+                            int n_views, double* out) {
+    hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)n_views), dim3(256), 0, st, partials, max_tiles, views, out);
     return hipGetLastError();
 }
 

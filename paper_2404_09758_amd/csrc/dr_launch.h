@@ -45,6 +45,8 @@ struct TileArgs {
     int act_pos;                     // scatter vertex groups
     int act_cls[DRD_MAX_TEX];        // scatter texel groups of each class
     int any_act;                     // any group is scattered
+    // loss mode: per (item, tile) partial sums
+    double* partials;
     // render mode
     float* out_rgb;
     unsigned* out_id;
@@ -78,7 +80,9 @@ struct StepArgs {
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
                         long long d, int words, int n_pairs, uint32_t* bits);
 hipError_t launch_setup(hipStream_t st, const SetupArgs& a, int n_items);
-hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, bool render, int n_items, int max_tiles);
+hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, int n_items, int max_tiles);
+hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tiles, const DViews& views,
+                            int n_views, double* out);
 hipError_t launch_check_tri(hipStream_t st, const int* tri, long long n, int n_verts, unsigned long long* bad);
 hipError_t launch_fold(hipStream_t st, const FoldArgs& a);
 hipError_t launch_step(hipStream_t st, const StepArgs& a);

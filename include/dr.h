@@ -120,6 +120,7 @@ typedef struct {
     uint64_t saturations;        /* loss differences clamped to |delta| = 32  */
     uint64_t nonfinite;          /* NaN differences dropped; non-finite
                                     gradients skipped by dr_step              */
+    uint64_t max_bin;            /* largest bin occupancy seen (triangles)    */
 } dr_stats_t;
 
 /* Create a context for one scene on the current HIP device; stream is a
@@ -129,6 +130,10 @@ dr_status dr_create(dr_ctx** out, const dr_scene* scene, const dr_tuning* tune, 
 dr_status dr_destroy(dr_ctx* ctx);
 dr_status dr_set_stream(dr_ctx* ctx, void* stream);
 dr_status dr_set_tuning(dr_ctx* ctx, const dr_tuning* tune);
+/* Counter word 3 of the sign stream of dr_estimate_grad (default 0): the
+ * index of this scene in a batch, so that a scene stepped alone draws the
+ * same signs as in a dr_batch. */
+dr_status dr_set_scene_index(dr_ctx* ctx, uint32_t scene_index);
 int64_t dr_param_count(const dr_ctx* ctx);       /* d                         */
 int64_t dr_group_count(const dr_ctx* ctx);       /* number of groups G        */
 
@@ -193,6 +198,49 @@ dr_status dr_timing_read(dr_ctx* ctx, dr_timing_t* out, int reset);
 /* Device-side condition counters since the last reset (synchronises). */
 dr_status dr_stats(dr_ctx* ctx, dr_stats_t* out);
 dr_status dr_reset_stats(dr_ctx* ctx);
+
+/* ---------------------------------------------------------------- batch
+ * The batching form: one optimisation step of many independent scenes of
+ * uneven size, each with n_pairs antithetic pairs over its views, run with
+ * one launch per kernel -- a persistent raster/shade/scatter kernel serves
+ * every (scene, pair, view, tile) unit from a work queue -- followed by one
+ * Adam/SGD launch over all scenes' parameters.  The step number lives on
+ * the device and advances with each step, so the whole step can be captured
+ * once as a HIP graph and replayed.  Scene b draws its signs with counter
+ * word 3 = b (dr_set_scene_index), so each scene's Q and K are those of
+ * dr_estimate_grad on that scene alone. */
+typedef struct dr_batch dr_batch;
+
+typedef struct {
+    dr_ctx* ctx;                 /* the scene (topology, UVs, textures, shading)  */
+    const dr_view* views;        /* host, copied; 1..16 views                     */
+    int32_t n_views;
+    const float* targets;        /* device: the views' [H,W,3] images, concatenated */
+    float* theta, * m, * v;      /* device [d]: parameters and Adam moments       */
+    int64_t* Q;                  /* device [d] and [G]: accumulators, zeroed by   */
+    uint32_t* K;                 /*   each step                                   */
+    float eps[1 + DR_MAX_TEX];   /* per block                                     */
+    float lr[1 + DR_MAX_TEX];    /* per block                                     */
+    int32_t bin_capacity;        /* 0: the context's tuning                       */
+} dr_batch_scene;
+
+/* Arrays passed in scenes[] must stay valid for the life of the batch.
+ * tile_px: 8, 16 or 32 for every scene; first_step >= 1. */
+dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scenes, int32_t n_scenes, int32_t n_pairs,
+                          int32_t tile_px, const dr_optim* opt, uint64_t seed, uint32_t first_step,
+                          void* stream);
+dr_status dr_batch_destroy(dr_batch* b);
+/* Eq. 8 summed over every scene's pairs and views into its Q and K, at the
+ * current step (the step counter does not advance). */
+dr_status dr_batch_estimate(dr_batch* b);
+/* One optimisation step of every scene (estimate, then descent), after
+ * which the step counter advances.  use_graph != 0 captures the step as a
+ * HIP graph on first use and replays it afterwards. */
+dr_status dr_batch_step(dr_batch* b, int use_graph);
+dr_status dr_batch_set_step(dr_batch* b, uint32_t step);      /* synchronous; step >= 1 */
+dr_status dr_batch_get_step(dr_batch* b, uint32_t* step);     /* synchronous */
+dr_status dr_batch_stats(dr_batch* b, dr_stats_t* out);       /* synchronous */
+const char* dr_batch_last_error(const dr_batch* b);
 
 const char* dr_status_str(dr_status s);
 const char* dr_last_error(const dr_ctx* ctx);     /* "" when none; ctx may be NULL */

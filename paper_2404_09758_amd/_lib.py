@@ -48,7 +48,15 @@ class Optim(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("tile_overflows", C.c_uint64), ("saturations", C.c_uint64), ("nonfinite", C.c_uint64)]
+    _fields_ = [("tile_overflows", C.c_uint64), ("saturations", C.c_uint64), ("nonfinite", C.c_uint64),
+                ("max_bin", C.c_uint64)]
+
+
+class BatchScene(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("views", C.POINTER(View)), ("n_views", C.c_int32),
+                ("targets", C.c_void_p), ("theta", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("Q", C.c_void_p), ("K", C.c_void_p), ("eps", C.c_float * (1 + MAX_TEX)),
+                ("lr", C.c_float * (1 + MAX_TEX)), ("bin_capacity", C.c_int32)]
 
 
 class Timing(C.Structure):
@@ -65,6 +73,7 @@ SIGNATURES = {
     "dr_destroy": (C.c_int, [_vp]),
     "dr_set_stream": (C.c_int, [_vp, _vp]),
     "dr_set_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "dr_set_scene_index": (C.c_int, [_vp, C.c_uint32]),
     "dr_param_count": (C.c_int64, [_vp]),
     "dr_group_count": (C.c_int64, [_vp]),
     "dr_render": (C.c_int, [_vp, _vp, C.POINTER(View), C.POINTER(Perturb), _vp, _vp, _vp]),
@@ -79,6 +88,15 @@ SIGNATURES = {
     "dr_timing_read": (C.c_int, [_vp, C.POINTER(Timing), C.c_int]),
     "dr_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
     "dr_reset_stats": (C.c_int, [_vp]),
+    "dr_batch_create": (C.c_int, [C.POINTER(_vp), C.POINTER(BatchScene), C.c_int32, C.c_int32, C.c_int32,
+                                  C.POINTER(Optim), C.c_uint64, C.c_uint32, _vp]),
+    "dr_batch_destroy": (C.c_int, [_vp]),
+    "dr_batch_estimate": (C.c_int, [_vp]),
+    "dr_batch_step": (C.c_int, [_vp, C.c_int]),
+    "dr_batch_set_step": (C.c_int, [_vp, C.c_uint32]),
+    "dr_batch_get_step": (C.c_int, [_vp, C.POINTER(C.c_uint32)]),
+    "dr_batch_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
+    "dr_batch_last_error": (C.c_char_p, [_vp]),
     "dr_status_str": (C.c_char_p, [C.c_int]),
     "dr_last_error": (C.c_char_p, [_vp]),
 }

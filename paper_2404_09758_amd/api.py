@@ -57,6 +57,16 @@ def _floats(vals, n):
     return arr
 
 
+def make_optim(kind, averaging, lr, beta1=0.9, beta2=0.999, eps_hat=1e-8) -> L.Optim:
+    o = L.Optim()
+    o.kind = int(kind)
+    o.averaging = int(averaging)
+    lr = list(lr) if lr is not None else []
+    o.lr = _floats(lr + [0.0] * (1 + L.MAX_TEX - len(lr)), 1 + L.MAX_TEX)
+    o.beta1, o.beta2, o.eps_hat = float(beta1), float(beta2), float(eps_hat)
+    return o
+
+
 class Context:
     """A scene bound to one GPU: topology, UVs, texture shapes and shading.
 
@@ -203,16 +213,13 @@ class Context:
 
     def step(self, theta, m, v, t, Q, K, eps, n_pairs, kind=ADAM, averaging=AVG_COUNT, lr=None,
              beta1=0.9, beta2=0.999, eps_hat=1e-8):
+        """One descent step (Adam or SGD) on theta; Q and K are zeroed."""
         dp = _check_tensor(theta, torch.float32, self.device, self.d, "theta")
         dm = _check_tensor(m, torch.float32, self.device, self.d, "m") if m is not None else 0
         dv = _check_tensor(v, torch.float32, self.device, self.d, "v") if v is not None else 0
         dq = _check_tensor(Q, torch.int64, self.device, self.d, "Q")
         dk = _check_tensor(K, torch.int32, self.device, self.G, "K")
-        o = L.Optim()
-        o.kind = int(kind)
-        o.averaging = int(averaging)
-        o.lr = _floats(list(lr) + [0.0] * (1 + L.MAX_TEX - len(lr)), 1 + L.MAX_TEX)
-        o.beta1, o.beta2, o.eps_hat = float(beta1), float(beta2), float(eps_hat)
+        o = make_optim(kind, averaging, lr, beta1, beta2, eps_hat)
         self._call("dr_step", C.c_void_p(dp), C.c_void_p(dm), C.c_void_p(dv), C.c_uint32(t), C.c_void_p(dq),
                    C.c_void_p(dk), self._eps(eps), int(n_pairs), C.byref(o))
 
@@ -224,10 +231,14 @@ class Context:
         self._call("dr_timing_read", C.byref(t), int(bool(reset)))
         return {k: getattr(t, k) for k, _ in L.Timing._fields_}
 
+    def set_scene_index(self, b):
+        self._call("dr_set_scene_index", C.c_uint32(b))
+
     def stats(self):
         s = L.Stats()
         self._call("dr_stats", C.byref(s))
-        return {"tile_overflows": s.tile_overflows, "saturations": s.saturations, "nonfinite": s.nonfinite}
+        return {"tile_overflows": s.tile_overflows, "saturations": s.saturations, "nonfinite": s.nonfinite,
+                "max_bin": s.max_bin}
 
     def reset_stats(self):
         self._call("dr_reset_stats")

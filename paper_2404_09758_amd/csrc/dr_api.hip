@@ -21,6 +21,7 @@ struct dr_ctx {
     dr_scene hs{};
     DScene sc{};
     dr_tuning tune{16, 256, 1};
+    uint32_t scene_index = 0;
     std::string err;
     TriR* recR = nullptr;
     TriS* recS = nullptr;
@@ -255,8 +256,8 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     sc.d = off;
     sc.G = goff;
     sc.words = (int)((off + 31) / 32);
-    if (hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc(&c->stats, ST_COUNT * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->stats, 0, ST_COUNT * sizeof(unsigned long long)) != hipSuccess) {
         (void)hipGetLastError();
         if (c->stats) (void)hipFree(c->stats);
         delete c;
@@ -264,8 +265,10 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     }
     // every vertex index must address the vertex array
     unsigned long long bad = 0;
-    bool ok = launch_check_tri(c->stream, s->tri, 3ll * s->n_tris, s->n_verts, c->stats + 3) == hipSuccess &&
-              hipMemcpyAsync(&bad, c->stats + 3, sizeof(bad), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+    bool ok = launch_check_tri(c->stream, s->tri, 3ll * s->n_tris, s->n_verts, c->stats + ST_BAD_INDEX) ==
+                  hipSuccess &&
+              hipMemcpyAsync(&bad, c->stats + ST_BAD_INDEX, sizeof(bad), hipMemcpyDeviceToHost, c->stream) ==
+                  hipSuccess &&
               hipStreamSynchronize(c->stream) == hipSuccess;
     if (!ok || bad != 0) {
         (void)hipGetLastError();
@@ -309,6 +312,12 @@ extern "C" dr_status dr_set_tuning(dr_ctx* c, const dr_tuning* t) {
         c->bin_entries = 0;
     }
     c->tune = *t;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_set_scene_index(dr_ctx* c, uint32_t scene_index) {
+    if (!c) return DR_E_INVALID;
+    c->scene_index = scene_index;
     return DR_OK;
 }
 
@@ -448,7 +457,9 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     DPert dp;
     dp.bits = c->bits;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = (b < 1 + c->sc.n_tex) ? eps[b] : 0.0f;
-    HIPCHK(c, timed(c, K_SIGNS, [&] { return launch_signs(c->stream, seed, step, 0u, 0u, c->sc.d, c->sc.words, n_pairs, c->bits); }));
+    HIPCHK(c, timed(c, K_SIGNS, [&] {
+        return launch_signs(c->stream, seed, step, 0u, c->scene_index, c->sc.d, c->sc.words, n_pairs, c->bits);
+    }));
 
     SetupArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -585,6 +596,21 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
 
 // ------------------------------------------------------- decode / step --
 
+// Adam constants, formed in double and rounded to float once.
+static OptimConst optim_const(const dr_optim* o, int averaging) {
+    OptimConst oc;
+    oc.kind = o->kind;
+    oc.averaging = averaging;
+    oc.b1 = o->beta1;
+    oc.b2 = o->beta2;
+    oc.omb1 = (float)(1.0 - (double)o->beta1);
+    oc.omb2 = (float)(1.0 - (double)o->beta2);
+    oc.eps_hat = o->eps_hat;
+    return oc;
+}
+
+static float bias_correction(float beta, uint32_t t) { return (float)(1.0 - std::pow((double)beta, (double)t)); }
+
 static dr_status step_common(dr_ctx* c, float* theta, float* m, float* v, uint32_t t, int64_t* Q, uint32_t* K,
                              const float* eps, int32_t n_pairs, const dr_optim* o, int averaging, float* grad) {
     dr_status s = check_eps(c, eps);
@@ -597,7 +623,7 @@ static dr_status step_common(dr_ctx* c, float* theta, float* m, float* v, uint32
     std::memset(&a, 0, sizeof(a));
     a.sc = c->sc;
     for (int b = 0; b < 1 + c->sc.n_tex; ++b) a.eps[b] = eps[b];
-    a.averaging = averaging;
+    a.oc.averaging = averaging;
     a.n_pairs = n_pairs;
     a.Q = (long long*)Q;
     a.K = K;
@@ -606,15 +632,10 @@ static dr_status step_common(dr_ctx* c, float* theta, float* m, float* v, uint32
         a.decode_only = 1;
         a.grad = grad;
     } else {
-        a.kind = o->kind;
+        a.oc = optim_const(o, averaging);
         for (int b = 0; b < 1 + c->sc.n_tex; ++b) a.lr[b] = o->lr[b];
-        a.b1 = o->beta1;
-        a.b2 = o->beta2;
-        a.omb1 = (float)(1.0 - (double)o->beta1);
-        a.omb2 = (float)(1.0 - (double)o->beta2);
-        a.bc1 = (float)(1.0 - std::pow((double)o->beta1, (double)t));
-        a.bc2 = (float)(1.0 - std::pow((double)o->beta2, (double)t));
-        a.eps_hat = o->eps_hat;
+        a.bc1 = bias_correction(o->beta1, t);
+        a.bc2 = bias_correction(o->beta2, t);
         a.theta = theta;
         a.m = m;
         a.v = v;
@@ -691,12 +712,13 @@ extern "C" dr_status dr_stats(dr_ctx* c, dr_stats_t* out) {
     if (!c || !out) return fail(c, DR_E_INVALID, "NULL argument");
     dr_status s = device_guard(c);
     if (s) return s;
-    unsigned long long h[4];
+    unsigned long long h[ST_COUNT];
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
-    out->tile_overflows = h[0];
-    out->saturations = h[1];
-    out->nonfinite = h[2];
+    out->tile_overflows = h[ST_OVERFLOWS];
+    out->saturations = h[ST_SATURATIONS];
+    out->nonfinite = h[ST_NONFINITE];
+    out->max_bin = h[ST_MAX_BIN];
     return DR_OK;
 }
 
@@ -704,7 +726,7 @@ extern "C" dr_status dr_reset_stats(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     dr_status s = device_guard(c);
     if (s) return s;
-    HIPCHK(c, hipMemsetAsync(c->stats, 0, 4 * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->stats, 0, ST_COUNT * sizeof(unsigned long long), c->stream));
     return DR_OK;
 }
 
@@ -720,3 +742,363 @@ extern "C" const char* dr_status_str(dr_status s) {
 }
 
 extern "C" const char* dr_last_error(const dr_ctx* c) { return c ? c->err.c_str() : ""; }
+
+// ============================================================== batch ==
+
+struct dr_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t gstream = nullptr;     // capture / replay stream of the graph
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+    BatchArgs args{};
+    int grid = 0;                      // persistent tile kernel workgroups
+    int n_scenes = 0;
+    // device allocations
+    std::vector<void*> allocs;
+    unsigned long long* stats = nullptr;
+};
+
+static dr_status bfail(dr_batch* b, dr_status s, const std::string& msg) {
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIPCHK(b, expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return bfail((b), DR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static void batch_free(dr_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    for (void* p : b->allocs)
+        if (p) (void)hipFree(p);
+    b->allocs.clear();
+}
+
+template <typename T>
+static dr_status balloc(dr_batch* b, T** p, size_t count, bool zero) {
+    void* q = nullptr;
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, DR_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    b->allocs.push_back(q);
+    if (zero && hipMemset(q, 0, bytes) != hipSuccess) return bfail(b, DR_E_HIP, "hipMemset failed");
+    *p = (T*)q;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scenes, int32_t n_scenes,
+                                     int32_t n_pairs, int32_t tile_px, const dr_optim* opt, uint64_t seed,
+                                     uint32_t first_step, void* stream) {
+    if (!out || !scenes || !opt) return DR_E_INVALID;
+    *out = nullptr;
+    if (n_scenes < 1 || n_scenes > (1 << 20)) return DR_E_INVALID;
+    if (n_pairs < 1 || n_pairs > 65535) return DR_E_INVALID;
+    if (tile_px != 8 && tile_px != 16 && tile_px != 32) return DR_E_INVALID;
+    if (first_step < 1) return DR_E_INVALID;
+    if (opt->kind != DR_ADAM && opt->kind != DR_SGD) return DR_E_INVALID;
+    if (opt->averaging != DR_AVG_COUNT && opt->averaging != DR_AVG_PAIRS) return DR_E_INVALID;
+    if (!(opt->beta1 >= 0.0f && opt->beta1 < 1.0f && opt->beta2 >= 0.0f && opt->beta2 < 1.0f) ||
+        !finite_nonneg(opt->eps_hat))
+        return DR_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DR_E_HIP;
+    for (int i = 0; i < n_scenes; ++i) {
+        const dr_batch_scene& s = scenes[i];
+        if (!s.ctx || !s.views || !s.targets || !s.theta || !s.Q || !s.K) return DR_E_INVALID;
+        if (s.ctx->device != dev) return DR_E_INVALID;
+        if (opt->kind == DR_ADAM && (!s.m || !s.v)) return DR_E_INVALID;
+        if (s.n_views < 1 || s.n_views > DR_MAX_VIEWS) return DR_E_INVALID;
+        if (s.bin_capacity < 0 || s.bin_capacity > (1 << 20)) return DR_E_INVALID;
+        for (int k = 0; k < 1 + s.ctx->sc.n_tex; ++k)
+            if (!finite_nonneg(s.eps[k]) || !std::isfinite(s.lr[k])) return DR_E_INVALID;
+        for (int v = 0; v < s.n_views; ++v)
+            if (check_view(nullptr, &s.views[v], tile_px) != DR_OK) return DR_E_INVALID;
+    }
+    dr_batch* b = new (std::nothrow) dr_batch();
+    if (!b) return DR_E_OOM;
+    b->device = dev;
+    b->stream = (hipStream_t)stream;
+    b->n_scenes = n_scenes;
+    BatchArgs& A = b->args;
+    std::memset(&A, 0, sizeof(A));
+    A.n_scenes = n_scenes;
+    A.n_pairs = n_pairs;
+    A.seed = seed;
+    A.tile = tile_px;
+    A.oc = optim_const(opt, opt->averaging);
+
+    // host tables
+    std::vector<BScene> hs(n_scenes);
+    std::vector<DView> hv;
+    std::vector<BItem> hi;
+    std::vector<int> order(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) order[i] = i;
+    // items of the costliest scenes first, so the queue ends on small units
+    auto cost = [&](int i) {
+        long long px = 0;
+        for (int v = 0; v < scenes[i].n_views; ++v) px += (long long)scenes[i].views[v].width * scenes[i].views[v].height;
+        return px;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    long long sign_blk = 0, group_blk = 0, rec = 0, cnt = 0, bin = 0, setup_blk = 0, tile0 = 0;
+    std::vector<long long> bits_off(n_scenes), R_off(n_scenes);
+    long long bits_total = 0, R_total = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        const dr_batch_scene& s = scenes[i];
+        BScene& S = hs[i];
+        std::memset(&S, 0, sizeof(S));
+        S.sc = s.ctx->sc;
+        S.theta = s.theta;
+        S.m = s.m;
+        S.v = s.v;
+        S.Q = (long long*)s.Q;
+        S.K = s.K;
+        S.targets = s.targets;
+        for (int k = 0; k <= DRD_MAX_TEX; ++k) {
+            S.eps[k] = (k < 1 + S.sc.n_tex) ? s.eps[k] : 0.0f;
+            S.lr[k] = (k < 1 + S.sc.n_tex) ? s.lr[k] : 0.0f;
+        }
+        S.act_pos = S.eps[0] != 0.0f;
+        S.any_act = S.act_pos;
+        for (int t = 0; t < S.sc.n_tex; ++t)
+            if (S.eps[1 + t] != 0.0f) {
+                S.act_cls[S.sc.tex_cls[t]] = 1;
+                S.any_act = 1;
+            }
+        S.n_views = s.n_views;
+        S.view0 = (int)hv.size();
+        S.scene_index = i;
+        long long tgt_off = 0;
+        for (int v = 0; v < s.n_views; ++v) {
+            hv.push_back(make_dview(s.views[v], tile_px, tgt_off));
+            tgt_off += 3ll * s.views[v].width * s.views[v].height;
+        }
+        long long nblk = (S.sc.d + 255) >> 8;
+        S.sign_blk0 = sign_blk;
+        sign_blk += (long long)n_pairs * ((nblk + 255) >> 8);
+        S.group_blk0 = group_blk;
+        group_blk += (S.sc.G + 255) >> 8;
+        bits_off[i] = bits_total;
+        bits_total += (long long)n_pairs * S.sc.words;
+        R_off[i] = R_total;
+        R_total += (long long)n_pairs * S.sc.G;
+    }
+    for (int oi = 0; oi < n_scenes; ++oi) {
+        int i = order[oi];
+        const dr_batch_scene& s = scenes[i];
+        const BScene& S = hs[i];
+        int cap = s.bin_capacity > 0 ? s.bin_capacity : s.ctx->tune.bin_capacity;
+        for (int n = 0; n < n_pairs; ++n)
+            for (int v = 0; v < s.n_views; ++v) {
+                const DView& dv = hv[S.view0 + v];
+                long long tiles = (long long)dv.tiles_x * dv.tiles_y;
+                BItem I;
+                std::memset(&I, 0, sizeof(I));
+                I.scene = i;
+                I.pair = n;
+                I.view = S.view0 + v;
+                I.cap = cap;
+                I.rec_off = rec;
+                rec += 2ll * S.sc.n_tris;
+                I.cnt_off = cnt;
+                cnt += 2 * tiles;
+                I.bin_off = bin;
+                bin += 2 * tiles * cap;
+                I.setup_blk0 = setup_blk;
+                setup_blk += 2 * (((long long)S.sc.n_tris + 255) >> 8);
+                I.tile0 = tile0;
+                tile0 += tiles;
+                hi.push_back(I);
+            }
+    }
+    if (sign_blk > 0x7fffffffll || setup_blk > 0x7fffffffll || group_blk > 0x7fffffffll) {
+        batch_free(b);
+        delete b;
+        return DR_E_UNSUPPORTED;
+    }
+    A.n_items = (int)hi.size();
+    A.sign_blocks = sign_blk;
+    A.setup_blocks = setup_blk;
+    A.group_blocks = group_blk;
+    A.total_tiles = tile0;
+
+    // Adam bias corrections by step, until both reach 1 in float
+    std::vector<float> bc1, bc2;
+    for (uint32_t t = 1; t <= (1u << 20); ++t) {
+        bc1.push_back(bias_correction(opt->beta1, t));
+        bc2.push_back(bias_correction(opt->beta2, t));
+        if (bc1.back() == 1.0f && bc2.back() == 1.0f) break;
+    }
+    A.n_bc = (int)bc1.size();
+
+    // device memory
+    dr_status st = DR_OK;
+    uint32_t* bits = nullptr;
+    long long* R = nullptr;
+    BScene* dsc = nullptr;
+    DView* dvw = nullptr;
+    BItem* dit = nullptr;
+    float *dbc1 = nullptr, *dbc2 = nullptr;
+    unsigned* dstep = nullptr;
+    unsigned long long* work = nullptr;
+    if ((st = balloc(b, &bits, (size_t)bits_total, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
+        (st = balloc(b, &A.recR, (size_t)rec, false)) || (st = balloc(b, &A.recS, (size_t)rec, false)) ||
+        (st = balloc(b, &A.counts, (size_t)cnt, true)) || (st = balloc(b, &A.bins, (size_t)bin, false)) ||
+        (st = balloc(b, &dsc, hs.size(), false)) || (st = balloc(b, &dvw, hv.size(), false)) ||
+        (st = balloc(b, &dit, hi.size(), false)) || (st = balloc(b, &dbc1, bc1.size(), false)) ||
+        (st = balloc(b, &dbc2, bc2.size(), false)) || (st = balloc(b, &dstep, 1, false)) ||
+        (st = balloc(b, &work, 1, true)) || (st = balloc(b, &b->stats, ST_COUNT, true))) {
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    for (int i = 0; i < n_scenes; ++i) {
+        hs[i].bits = bits + bits_off[i];
+        hs[i].R = R + R_off[i];
+    }
+    bool ok = hipMemcpy(dsc, hs.data(), hs.size() * sizeof(BScene), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dvw, hv.data(), hv.size() * sizeof(DView), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dit, hi.data(), hi.size() * sizeof(BItem), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dbc1, bc1.data(), bc1.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dbc2, bc2.data(), bc2.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dstep, &first_step, sizeof(unsigned), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        batch_free(b);
+        delete b;
+        return DR_E_HIP;
+    }
+    A.scenes = dsc;
+    A.views = dvw;
+    A.items = dit;
+    A.bc1 = dbc1;
+    A.bc2 = dbc2;
+    A.step = dstep;
+    A.work = work;
+    A.stats = b->stats;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    b->grid = cus * batch_tile_blocks_per_cu(tile_px);
+    *out = b;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_destroy(dr_batch* b) {
+    if (!b) return DR_E_INVALID;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+    batch_free(b);
+    delete b;
+    return DR_OK;
+}
+
+static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend) {
+    const BatchArgs& A = b->args;
+    hipError_t e;
+    if ((e = launch_batch_begin(st, A)) != hipSuccess) return e;
+    if ((e = launch_batch_signs(st, A)) != hipSuccess) return e;
+    if ((e = launch_batch_setup(st, A)) != hipSuccess) return e;
+    if ((e = launch_batch_tile(st, A, b->grid)) != hipSuccess) return e;
+    if ((e = launch_batch_fold(st, A)) != hipSuccess) return e;
+    if (descend) {
+        if ((e = launch_batch_step(st, A)) != hipSuccess) return e;
+        if ((e = launch_batch_end(st, A)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static dr_status batch_device(dr_batch* b) {
+    int cur = -1;
+    BHIPCHK(b, hipGetDevice(&cur));
+    if (cur != b->device) BHIPCHK(b, hipSetDevice(b->device));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_estimate(dr_batch* b) {
+    if (!b) return DR_E_INVALID;
+    dr_status s = batch_device(b);
+    if (s) return s;
+    BHIPCHK(b, batch_enqueue(b, b->stream, false));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
+    if (!b) return DR_E_INVALID;
+    dr_status s = batch_device(b);
+    if (s) return s;
+    if (!use_graph) {
+        BHIPCHK(b, batch_enqueue(b, b->stream, true));
+        return DR_OK;
+    }
+    if (!b->exec) {
+        // capture on a stream of our own (the caller's may be the null
+        // stream, which cannot be captured); order it after the caller's
+        // stream with events on every replay
+        BHIPCHK(b, hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking));
+        BHIPCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+        BHIPCHK(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+        BHIPCHK(b, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = batch_enqueue(b, b->gstream, true);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->gstream, &g);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return bfail(b, DR_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        b->graph = g;
+        BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    BHIPCHK(b, hipEventRecord(b->ev_in, b->stream));
+    BHIPCHK(b, hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+    BHIPCHK(b, hipGraphLaunch(b->exec, b->gstream));
+    BHIPCHK(b, hipEventRecord(b->ev_out, b->gstream));
+    BHIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_set_step(dr_batch* b, uint32_t step) {
+    if (!b) return DR_E_INVALID;
+    if (step < 1) return bfail(b, DR_E_INVALID, "step must be >= 1");
+    dr_status s = batch_device(b);
+    if (s) return s;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (b->gstream) BHIPCHK(b, hipStreamSynchronize(b->gstream));
+    BHIPCHK(b, hipMemcpy((void*)b->args.step, &step, sizeof(step), hipMemcpyHostToDevice));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_get_step(dr_batch* b, uint32_t* step) {
+    if (!b || !step) return DR_E_INVALID;
+    dr_status s = batch_device(b);
+    if (s) return s;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (b->gstream) BHIPCHK(b, hipStreamSynchronize(b->gstream));
+    BHIPCHK(b, hipMemcpy(step, b->args.step, sizeof(*step), hipMemcpyDeviceToHost));
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_stats(dr_batch* b, dr_stats_t* out) {
+    if (!b || !out) return DR_E_INVALID;
+    dr_status s = batch_device(b);
+    if (s) return s;
+    unsigned long long h[ST_COUNT];
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (b->gstream) BHIPCHK(b, hipStreamSynchronize(b->gstream));
+    BHIPCHK(b, hipMemcpy(h, b->stats, sizeof(h), hipMemcpyDeviceToHost));
+    out->tile_overflows = h[ST_OVERFLOWS];
+    out->saturations = h[ST_SATURATIONS];
+    out->nonfinite = h[ST_NONFINITE];
+    out->max_bin = h[ST_MAX_BIN];
+    return DR_OK;
+}
+
+extern "C" const char* dr_batch_last_error(const dr_batch* b) { return b ? b->err.c_str() : ""; }

@@ -2,32 +2,31 @@
 // estimator for gfx950 (MI355X).
 //
 // Pipeline of one estimate (Sec. 4.3, Alg. 1 and 2, Eq. 8-9):
-//   k_signs      Philox sign bits of every pair             (shader P)
-//   k_setup_bin  per (item, sign, triangle): perturb the three vertices,
-//                project, snap, build the raster record and append the
-//                triangle to the bins of the tiles its bbox touches
-//   k_tile       per (item, tile): rasterise the + and - scenes into LDS
-//                depth|id keys (64-bit atomic min), shade both winners,
-//                form the per-pixel loss difference and scatter it to the
-//                union of the pixel's contribution groups    (R and G fused)
-//   k_fold       Q_i += sum_n s_i^(n) R^(n)_g(i): the per-group sums of
-//                each pair become per-parameter fixed-point sums
-//   k_step       decode, per-parameter average, Adam / SGD   (shader D)
-// An "item" is one (pair, view).  Triangle records, bins and the per-pair
-// group sums R live in context scratch memory.
+//   signs      Philox sign bits of every pair                  (shader P)
+//   setup      per (item, sign, triangle): perturb the three vertices,
+//              project, snap, build the raster record and append the
+//              triangle to the bins of the tiles its bbox touches
+//   tile       per (item, tile): rasterise the + and - scenes into LDS
+//              depth|id keys (64-bit atomic min), shade both winners,
+//              form the per-pixel loss difference and scatter it to the
+//              union of the pixel's contribution groups     (R and G fused)
+//   fold       Q_i += sum_n s_i^(n) R^(n)_g(i): the per-group sums of each
+//              pair become per-parameter fixed-point sums
+//   step       decode, per-parameter average, Adam / SGD    (shader D)
+// An "item" is one (pair, view) of a scene.  The single-scene kernels take
+// their descriptors as kernel arguments; the batch kernels read them from
+// device memory and cover many scenes per launch.  Both share the bodies
+// below, so they compute the same bits.
 #include "dr_launch.h"
 
-// ------------------------------------------------------------ k_signs --
 
-__global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
-                        long long d, int words, uint32_t* __restrict__ bits) {
-    long long blk = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int p = blockIdx.y;
-    long long nblk = (d + 255) >> 8;
-    if (blk >= nblk) return;
+// ---------------------------------------------------------------- signs --
+
+// Philox block `blk` of pair `pair`: 256 signs, written as 8 uint32 words.
+__device__ __forceinline__ void signs_block(unsigned long long seed, unsigned step, unsigned pair, unsigned scene,
+                                            long long blk, int words, uint32_t* __restrict__ out) {
     unsigned long long r[4];
-    philox4x64_10((unsigned long long)blk, (unsigned long long)(pair0 + p), step, scene, seed, 0ull, r);
-    uint32_t* out = bits + (long long)p * words;
+    philox4x64_10((unsigned long long)blk, (unsigned long long)pair, step, scene, seed, 0ull, r);
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
         long long word = blk * 8 + w;
@@ -35,21 +34,24 @@ __global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, 
     }
 }
 
-// -------------------------------------------------------- k_setup_bin --
+__global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
+                        long long d, int words, uint32_t* __restrict__ bits) {
+    long long blk = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int p = blockIdx.y;
+    long long nblk = (d + 255) >> 8;
+    if (blk >= nblk) return;
+    signs_block(seed, step, pair0 + p, scene, blk, words, bits + (long long)p * words);
+}
 
-__global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
-    const DScene& sc = a.sc;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= sc.n_tris) return;
-    int slot = blockIdx.y;                       // (local item, sign)
-    int li = slot / a.nsign, s = slot % a.nsign;
-    int item = a.item0 + li;
-    int pair = item / a.n_views, view = item % a.n_views;
-    const DView& vw = a.views.v[view];
-    const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
-    float sgn = a.sgn[s];
-    float e0 = a.pert.eps[0];
+// ---------------------------------------------------------------- setup --
 
+// Triangle t of one (item, sign): perturbed vertices, projection, snap,
+// setup record, and its entries in the bins of the tiles it may cover.
+__device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
+                                          const uint32_t* __restrict__ pb, float e0, float sgn, int t,
+                                          TriR* __restrict__ recR, TriS* __restrict__ recS,
+                                          unsigned* __restrict__ counts, unsigned* __restrict__ bins, int tile_px,
+                                          int cap) {
     int vid[3];
     float p[9];
     Vtx v[3];
@@ -57,16 +59,15 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     for (int k = 0; k < 3; ++k) {
         vid[k] = sc.tri[3 * (long long)t + k];
         long long base = 3 * (long long)vid[k];
-        p[3 * k + 0] = pval(a.theta, base + 0, e0, pb, sgn);
-        p[3 * k + 1] = pval(a.theta, base + 1, e0, pb, sgn);
-        p[3 * k + 2] = pval(a.theta, base + 2, e0, pb, sgn);
+        p[3 * k + 0] = pval(theta, base + 0, e0, pb, sgn);
+        p[3 * k + 1] = pval(theta, base + 1, e0, pb, sgn);
+        p[3 * k + 2] = pval(theta, base + 2, e0, pb, sgn);
         v[k] = xform(vw, p[3 * k + 0], p[3 * k + 1], p[3 * k + 2]);
     }
     TriR r;
     TriS sh;
     r.flags = 0u;
     r.pad[0] = 0; r.pad[1] = 0;
-    long long rec = (long long)slot * sc.n_tris + t;
     bool ok = v[0].valid && v[1].valid && v[2].valid;
     long long area2 = 0;
     if (ok) {
@@ -75,8 +76,7 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
         ok = area2 != 0;
     }
     if (!ok) {
-        r.flags = 0u;
-        a.recR[rec] = r;
+        recR[t] = r;                 // flags 0: culled
         return;
     }
     bool sw = area2 < 0;
@@ -115,20 +115,33 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     for (int k = 0; k < 9; ++k) sh.p[k] = p[k];
     sh.vid[0] = vid[0]; sh.vid[1] = vid[1]; sh.vid[2] = vid[2];
     sh.pad = 0;
-    a.recR[rec] = r;
-    a.recS[rec] = sh;
+    recR[t] = r;
+    recS[t] = sh;
     if (bx0 > bx1) return;
-    int tx0 = bx0 / a.tile, tx1 = bx1 / a.tile, ty0 = by0 / a.tile, ty1 = by1 / a.tile;
-    long long tbase = (long long)slot * a.max_tiles;
+    int tx0 = bx0 / tile_px, tx1 = bx1 / tile_px, ty0 = by0 / tile_px, ty1 = by1 / tile_px;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
-            long long tile = tbase + ty * vw.tiles_x + tx;
-            unsigned k = atomicAdd(&a.counts[tile], 1u);
-            if (k < (unsigned)a.cap) a.bins[tile * a.cap + k] = (unsigned)t;
+            long long tile = (long long)ty * vw.tiles_x + tx;
+            unsigned k = atomicAdd(&counts[tile], 1u);
+            if (k < (unsigned)cap) bins[tile * cap + k] = (unsigned)t;
         }
 }
 
-// ------------------------------------------------------------- k_tile --
+__global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
+    const DScene& sc = a.sc;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sc.n_tris) return;
+    int slot = blockIdx.y;                       // (local item, sign)
+    int li = slot / a.nsign, s = slot % a.nsign;
+    int item = a.item0 + li;
+    int pair = item / a.n_views, view = item % a.n_views;
+    const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
+    setup_tri(sc, a.views.v[view], a.theta, pb, a.pert.eps[0], a.sgn[s], t, a.recR + (long long)slot * sc.n_tris,
+              a.recS + (long long)slot * sc.n_tris, a.counts + (long long)slot * a.max_tiles,
+              a.bins + (long long)slot * a.max_tiles * a.cap, a.tile, a.cap);
+}
+
+// ----------------------------------------------------------------- tile --
 
 // Map consecutive workgroups (which the dispatcher spreads round-robin over
 // the 8 XCDs) to contiguous runs of tiles per XCD, so neighbouring tiles --
@@ -241,39 +254,69 @@ struct TileCfg {
     static constexpr int LOG2T = TILE == 8 ? 9 : (TILE == 16 ? 10 : 11);
 };
 
+
+// Everything the tile body needs, resolved by the kernel's prologue.
+struct TileJob {
+    const DScene* sc;
+    const DView* vw;
+    const float* theta;
+    const uint32_t* pb;                  // sign bits of the pair (null: unperturbed)
+    const float* eps;                    // per block
+    float sgn[2];
+    const TriR* recR[2];                 // records of each sign (index = triangle)
+    const TriS* recS[2];
+    unsigned* counts[2];                 // bin counters of each sign (index = tile)
+    const unsigned* bins[2];             // bin entries of each sign (tile * cap + k)
+    int cap;
+    int tile;
+    unsigned long long* stats;
+    // estimate
+    const float* targets;                // this view's target image
+    long long* Rp;                       // group sums of the pair
+    unsigned* K;
+    int act_pos, any_act;
+    const int* act_cls;
+    // render
+    float* out_rgb;
+    unsigned* out_id;
+    float* out_uv;
+    // loss
+    double* partial;
+};
+
 // MODE: 0 estimate (both signs, scatter), 1 render (write rgb/id/uv),
 // 2 loss (per-tile sum of the per-pixel L2 error f_{w,h}).
 template <int TILE, int MODE>
-__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile(TileArgs a) {
-    constexpr bool RENDER = MODE != 0;
-    constexpr int NPIX = TILE * TILE;
-    constexpr int PPT = NPIX > 256 ? NPIX / 256 : 1;
-    constexpr int TB = NPIX / PPT;
-    constexpr int NW = TB / 64;
-    constexpr int NS = RENDER ? 1 : 2;
-    constexpr int LOG2T = TileCfg<TILE>::LOG2T;
-    constexpr int TSIZE = 1 << LOG2T;
-    __shared__ unsigned long long key[NS][NPIX];
+struct TileShared {
+    static constexpr int NPIX = TILE * TILE;
+    static constexpr int PPT = NPIX > 256 ? NPIX / 256 : 1;
+    static constexpr int TB = NPIX / PPT;
+    static constexpr int NS = MODE == 0 ? 2 : 1;
+    static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
+    unsigned long long key[NS][NPIX];
+    GroupTable<LOG2T> table;
+    double red[MODE == 2 ? TB : 1];
+};
 
-    const DScene& sc = a.sc;
-    int li = blockIdx.y;
-    int item = a.item0 + li;
-    int pair = item / a.n_views, view = item % a.n_views;
-    const DView& vw = a.views.v[view];
-    int ntiles = vw.tiles_x * vw.tiles_y;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    int tx = tile % vw.tiles_x, ty = tile / vw.tiles_x;
+template <int TILE, int MODE>
+__device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MODE>& S) {
+    using SH = TileShared<TILE, MODE>;
+    constexpr int NPIX = SH::NPIX, PPT = SH::PPT, TB = SH::TB, NS = SH::NS;
+    constexpr int NW = TB / 64;
+    constexpr int LOG2T = SH::LOG2T;
+    constexpr int TSIZE = 1 << LOG2T;
+    const DScene& sc = *J.sc;
+    const DView& vw = *J.vw;
+    int tx = J.tile % vw.tiles_x, ty = J.tile / vw.tiles_x;
     int px0 = tx * TILE, py0 = ty * TILE;
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    for (int j = tid; j < NS * NPIX; j += TB) (&key[0][0])[j] = ~0ull;
-    __shared__ GroupTable<RENDER ? 1 : LOG2T> table;
-    if constexpr (!RENDER) {
+    for (int j = tid; j < NS * NPIX; j += TB) (&S.key[0][0])[j] = ~0ull;
+    if constexpr (MODE == 0) {
         for (int j = tid; j < TSIZE; j += TB) {
-            table.key[j] = HASH_EMPTY;
-            table.sum[j] = 0ull;
-            table.cnt[j] = 0u;
+            S.table.key[j] = HASH_EMPTY;
+            S.table.sum[j] = 0ull;
+            S.table.cnt[j] = 0u;
         }
     }
     __syncthreads();
@@ -281,23 +324,21 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     unsigned cnt[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        int slot = li * NS + s;
-        long long tslot = (long long)slot * a.max_tiles + tile;
-        cnt[s] = a.counts[tslot];
-        const TriR* __restrict__ R = a.recR + (long long)slot * sc.n_tris;
-        if (cnt[s] <= (unsigned)a.cap) {
-            const unsigned* __restrict__ list = a.bins + tslot * a.cap;
+        cnt[s] = J.counts[s][J.tile];
+        const TriR* __restrict__ R = J.recR[s];
+        if (cnt[s] <= (unsigned)J.cap) {
+            const unsigned* __restrict__ list = J.bins[s] + (long long)J.tile * J.cap;
             for (unsigned k = wave; k < cnt[s]; k += NW) {
                 unsigned t = __builtin_amdgcn_readfirstlane(list[k]);
                 TriR r = R[t];
-                raster_tri<TILE>(r, t, px0, py0, lane, key[s]);
+                raster_tri<TILE>(r, t, px0, py0, lane, S.key[s]);
             }
         } else {
             // bin overflow: test every triangle against this tile
             for (int t = wave; t < sc.n_tris; t += NW) {
                 TriR r = R[t];
                 if (!(r.flags & TRI_VALID)) continue;
-                raster_tri<TILE>(r, (unsigned)t, px0, py0, lane, key[s]);
+                raster_tri<TILE>(r, (unsigned)t, px0, py0, lane, S.key[s]);
             }
         }
     }
@@ -305,14 +346,12 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     if (tid == 0) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            long long tslot = (long long)(li * NS + s) * a.max_tiles + tile;
-            a.counts[tslot] = 0u;                // leave the bin empty for the next use
-            if (cnt[s] > (unsigned)a.cap) atomicAdd(&a.stats[0], 1ull);
+            J.counts[s][J.tile] = 0u;            // leave the bin empty for the next use
+            if (cnt[s] > (unsigned)J.cap) atomicAdd(&J.stats[ST_OVERFLOWS], 1ull);
+            atomicMax(&J.stats[ST_MAX_BIN], (unsigned long long)cnt[s]);
         }
     }
 
-    const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
-    long long* Rp = RENDER ? nullptr : a.R + (long long)pair * sc.G;
     double loss_acc = 0.0;
     for (int j = 0; j < PPT; ++j) {
         int local = tid + j * TB;
@@ -325,44 +364,43 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
         int vids[NS][3];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            unsigned long long k = inpix ? key[s][local] : ~0ull;
+            unsigned long long k = inpix ? S.key[s][local] : ~0ull;
             id[s] = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
             rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
             uv[s][0] = 0.0f; uv[s][1] = 0.0f;
             vids[s][0] = vids[s][1] = vids[s][2] = -1;
             if (id[s] != DRD_BG) {
-                long long rec = (long long)(li * NS + s) * sc.n_tris + id[s];
-                TriR r = a.recR[rec];
-                TriS sh = a.recS[rec];
-                shade_pixel(sc, vw, a.theta, pb, a.pert.eps, a.sgn[s], r, sh, (int)id[s], px, py, rgb[s], uv[s]);
+                TriR r = J.recR[s][id[s]];
+                TriS sh = J.recS[s][id[s]];
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, (int)id[s], px, py, rgb[s], uv[s]);
                 vids[s][0] = sh.vid[0]; vids[s][1] = sh.vid[1]; vids[s][2] = sh.vid[2];
             }
         }
         long long pix = (long long)y * vw.W + x;
         if constexpr (MODE == 2) {
             if (inpix) {
-                const float* tg = a.targets + vw.tgt_off + 3 * pix;
+                const float* tg = J.targets + 3 * pix;
                 float dr = rgb[0][0] - tg[0], dg = rgb[0][1] - tg[1], db = rgb[0][2] - tg[2];
                 loss_acc += (double)((dr * dr + dg * dg) + db * db);
             }
         } else if constexpr (MODE == 1) {
             if (!inpix) continue;
-            if (a.out_rgb) {
-                a.out_rgb[3 * pix + 0] = rgb[0][0];
-                a.out_rgb[3 * pix + 1] = rgb[0][1];
-                a.out_rgb[3 * pix + 2] = rgb[0][2];
+            if (J.out_rgb) {
+                J.out_rgb[3 * pix + 0] = rgb[0][0];
+                J.out_rgb[3 * pix + 1] = rgb[0][1];
+                J.out_rgb[3 * pix + 2] = rgb[0][2];
             }
-            if (a.out_id) a.out_id[pix] = id[0];
-            if (a.out_uv) {
-                a.out_uv[2 * pix + 0] = uv[0][0];
-                a.out_uv[2 * pix + 1] = uv[0][1];
+            if (J.out_id) J.out_id[pix] = id[0];
+            if (J.out_uv) {
+                J.out_uv[2 * pix + 0] = uv[0][0];
+                J.out_uv[2 * pix + 1] = uv[0][1];
             }
         } else {
             // an empty contribution set (background in both renders) adds nothing
-            bool act = inpix && (id[0] != DRD_BG || id[1] != DRD_BG) && a.any_act;
+            bool act = inpix && (id[0] != DRD_BG || id[1] != DRD_BG) && J.any_act;
             long long q = 0;
             if (act) {
-                const float* tg = a.targets + vw.tgt_off + 3 * pix;
+                const float* tg = J.targets + 3 * pix;
                 float t0 = tg[0], t1 = tg[1], t2 = tg[2];
                 float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
                 float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
@@ -370,31 +408,31 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
                 float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
                 int flag;
                 q = quantize(fp - fm, flag);
-                if (flag) atomicAdd(&a.stats[flag], 1ull);
+                if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
-            if (a.act_pos) {
+            if (J.act_pos) {
                 // same triangle in both renders: combined per wave
                 bool same = act && id[0] == id[1];
-                wave_vertices<LOG2T>(table, Rp, a.K, same, id[0], vids[0][0], vids[0][1], vids[0][2], q);
+                wave_vertices<LOG2T>(S.table, J.Rp, J.K, same, id[0], vids[0][0], vids[0][1], vids[0][2], q);
                 if (act && !same) {
                     // the union of the two triangles' vertices, each once
                     if (id[0] != DRD_BG) {
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) table_add<LOG2T>(table, Rp, a.K, (unsigned)vids[0][k], q, 1u);
+                        for (int k = 0; k < 3; ++k) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)vids[0][k], q, 1u);
                     }
                     if (id[1] != DRD_BG) {
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
                             int g = vids[1][k];
                             bool dup = (g == vids[0][0]) || (g == vids[0][1]) || (g == vids[0][2]);
-                            if (!dup) table_add<LOG2T>(table, Rp, a.K, (unsigned)g, q, 1u);
+                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
                         }
                     }
                 }
             }
             if (act) {
                 for (int c = 0; c < sc.n_cls; ++c) {
-                    if (!a.act_cls[c]) continue;
+                    if (!J.act_cls[c]) continue;
                     int W = sc.cls_w[c], H = sc.cls_h[c];
                     long long base = sc.cls_goff[c];
                     long long gs[NS][4];
@@ -429,7 +467,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
                                 for (int j2 = 0; j2 < 4; ++j2)
                                     if (gs[0][j2] == g) dup = true;
                             }
-                            if (!dup) table_add<LOG2T>(table, Rp, a.K, (unsigned)g, q, 1u);
+                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
                         }
                 }
             }
@@ -437,22 +475,64 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     }
     if constexpr (MODE == 2) {
         // fixed-order tree reduction of the tile's per-pixel errors
-        __shared__ double red[TB];
-        red[tid] = loss_acc;
+        S.red[tid] = loss_acc;
         __syncthreads();
         for (int w = TB / 2; w > 0; w >>= 1) {
-            if (tid < w) red[tid] = red[tid] + red[tid + w];
+            if (tid < w) S.red[tid] = S.red[tid] + S.red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) a.partials[(long long)li * a.max_tiles + tile] = red[0];
+        if (tid == 0) *J.partial = S.red[0];
     }
-    if constexpr (!RENDER) {
+    if constexpr (MODE == 0) {
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
-            unsigned g = table.key[j];
-            if (g != HASH_EMPTY) global_add(Rp, a.K, (long long)g, (long long)table.sum[j], table.cnt[j]);
+            unsigned g = S.table.key[j];
+            if (g != HASH_EMPTY) global_add(J.Rp, J.K, (long long)g, (long long)S.table.sum[j], S.table.cnt[j]);
         }
     }
+}
+
+template <int TILE, int MODE>
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile(TileArgs a) {
+    __shared__ TileShared<TILE, MODE> S;
+    constexpr int NS = TileShared<TILE, MODE>::NS;
+    const DScene& sc = a.sc;
+    int li = blockIdx.y;
+    int item = a.item0 + li;
+    int pair = item / a.n_views, view = item % a.n_views;
+    const DView& vw = a.views.v[view];
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= vw.tiles_x * vw.tiles_y) return;
+    TileJob J;
+    J.sc = &a.sc;
+    J.vw = &vw;
+    J.theta = a.theta;
+    J.pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
+    J.eps = a.pert.eps;
+    J.sgn[0] = a.sgn[0];
+    J.sgn[1] = a.sgn[1];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        int slot = li * NS + (s < NS ? s : 0);
+        J.recR[s] = a.recR + (long long)slot * sc.n_tris;
+        J.recS[s] = a.recS + (long long)slot * sc.n_tris;
+        J.counts[s] = a.counts + (long long)slot * a.max_tiles;
+        J.bins[s] = a.bins + (long long)slot * a.max_tiles * a.cap;
+    }
+    J.cap = a.cap;
+    J.tile = tile;
+    J.stats = a.stats;
+    J.targets = a.targets ? a.targets + vw.tgt_off : nullptr;
+    J.Rp = (MODE == 0) ? a.R + (long long)pair * sc.G : nullptr;
+    J.K = a.K;
+    J.act_pos = a.act_pos;
+    J.any_act = a.any_act;
+    J.act_cls = a.act_cls;
+    J.out_rgb = a.out_rgb;
+    J.out_id = a.out_id;
+    J.out_uv = a.out_uv;
+    J.partial = a.partials ? a.partials + (long long)li * a.max_tiles + tile : nullptr;
+    tile_body<TILE, MODE>(J, S);
 }
 
 template __global__ void k_tile<8, 0>(TileArgs);
@@ -483,7 +563,7 @@ __global__ void __launch_bounds__(256) k_sum_tiles(const double* __restrict__ pa
     if (tid == 0) out[v] = red[0];
 }
 
-// ------------------------------------------------------------- k_fold --
+// -------------------------------------------------------------- fold --
 
 // Parameters of group g: a vertex's x, y, z, or a texel's channels in
 // every texture of its class.  Calls fn(param index, block).
@@ -507,61 +587,75 @@ __device__ __forceinline__ void for_params(const DScene& sc, long long g, Fn fn)
     }
 }
 
-__global__ void __launch_bounds__(256) k_fold(FoldArgs a) {
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const DScene& sc = a.sc;
-    if (g >= sc.G) return;
+__device__ __forceinline__ void fold_group(const DScene& sc, long long g, long long* __restrict__ R,
+                                           const uint32_t* __restrict__ bits, int n_pairs, const float* eps,
+                                           long long* __restrict__ Q) {
     for_params(sc, g, [&](long long i, int b) {
-        if (a.eps[b] == 0.0f) return;
+        if (eps[b] == 0.0f) return;
         long long acc = 0;
-        for (int n = 0; n < a.n_pairs; ++n) {
-            long long r = a.R[(long long)n * sc.G + g];
-            acc += (sign_of(a.bits + (long long)n * sc.words, i) > 0) ? r : -r;
+        for (int n = 0; n < n_pairs; ++n) {
+            long long r = R[(long long)n * sc.G + g];
+            acc += (sign_of(bits + (long long)n * sc.words, i) > 0) ? r : -r;
         }
-        if (acc != 0) a.Q[i] += acc;
+        if (acc != 0) Q[i] += acc;
     });
-    for (int n = 0; n < a.n_pairs; ++n) a.R[(long long)n * sc.G + g] = 0;
+    for (int n = 0; n < n_pairs; ++n) R[(long long)n * sc.G + g] = 0;
 }
 
-// ----------------------------------------------------- k_step / decode --
-
-__global__ void __launch_bounds__(256) k_step(StepArgs a) {
+__global__ void __launch_bounds__(256) k_fold(FoldArgs a) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const DScene& sc = a.sc;
-    if (g >= sc.G) return;
-    unsigned kc = a.K[g];
-    double D = (a.averaging == 0) ? (double)kc : (double)a.n_pairs;
+    if (g >= a.sc.G) return;
+    fold_group(a.sc, g, a.R, a.bits, a.n_pairs, a.eps, a.Q);
+}
+
+// ------------------------------------------------------ step / decode --
+
+__device__ __forceinline__ void step_group(const DScene& sc, long long g, const float* eps, const float* lr,
+                                           int n_pairs, const OptimConst& oc, float bc1, float bc2,
+                                           int decode_only, float* __restrict__ theta, float* __restrict__ m,
+                                           float* __restrict__ v, long long* __restrict__ Q,
+                                           unsigned* __restrict__ K, float* __restrict__ grad,
+                                           unsigned long long* __restrict__ stats) {
+    unsigned kc = K[g];
+    double D = (oc.averaging == 0) ? (double)kc : (double)n_pairs;
     for_params(sc, g, [&](long long i, int b) {
-        float e = a.eps[b];
-        long long qv = a.Q[i];
+        float e = eps[b];
+        long long qv = Q[i];
         float gi = 0.0f;
         if (e != 0.0f && D != 0.0)
             gi = (float)(((double)qv * (1.0 / 4294967296.0)) / (2.0 * (double)e * D));
-        if (a.decode_only) {
-            a.grad[i] = gi;
+        if (decode_only) {
+            grad[i] = gi;
             return;
         }
-        a.Q[i] = 0;
+        Q[i] = 0;
         if (e == 0.0f) return;
-        if (a.averaging == 0 && kc == 0u) return;
+        if (oc.averaging == 0 && kc == 0u) return;
         if (!(fabsf(gi) <= 3.402823466e38f)) {
-            atomicAdd(&a.stats[2], 1ull);
+            atomicAdd(&stats[ST_NONFINITE], 1ull);
             return;
         }
-        float lr = a.lr[b];
-        if (a.kind == 1) {
-            a.theta[i] = a.theta[i] - lr * gi;
+        float l = lr[b];
+        if (oc.kind == 1) {
+            theta[i] = theta[i] - l * gi;
         } else {
-            float mi = a.b1 * a.m[i] + a.omb1 * gi;
-            float vi = a.b2 * a.v[i] + a.omb2 * (gi * gi);
-            a.m[i] = mi;
-            a.v[i] = vi;
-            float mh = mi / a.bc1;
-            float vh = vi / a.bc2;
-            a.theta[i] = a.theta[i] - lr * (mh / (sqrtf(vh) + a.eps_hat));
+            float mi = oc.b1 * m[i] + oc.omb1 * gi;
+            float vi = oc.b2 * v[i] + oc.omb2 * (gi * gi);
+            m[i] = mi;
+            v[i] = vi;
+            float mh = mi / bc1;
+            float vh = vi / bc2;
+            theta[i] = theta[i] - l * (mh / (sqrtf(vh) + oc.eps_hat));
         }
     });
-    if (!a.decode_only) a.K[g] = 0u;
+    if (!decode_only) K[g] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_step(StepArgs a) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.sc.G) return;
+    step_group(a.sc, g, a.eps, a.lr, a.n_pairs, a.oc, a.bc1, a.bc2, a.decode_only, a.theta, a.m, a.v, a.Q, a.K,
+               a.grad, a.stats);
 }
 
 // -------------------------------------------------------- k_check_tri --
@@ -574,6 +668,142 @@ __global__ void k_check_tri(const int* __restrict__ tri, long long n, int n_vert
     if (i >= n) return;
     int v = tri[i];
     if (v < 0 || v >= n_verts) atomicAdd(bad, 1ull);
+}
+
+// -------------------------------------------------------------- batch --
+
+// Index of the last entry of a non-decreasing sequence (stride in bytes
+// between entries, starting at `first`) that is <= x; n >= 1 entries.
+__device__ __forceinline__ int last_le(const char* first, int stride, int n, long long x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        long long v = *(const long long*)(first + (long long)mid * stride);
+        if (v <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_batch_begin(unsigned long long* work) { *work = 0ull; }
+
+__global__ void k_batch_end(unsigned* step) { *step = *step + 1u; }
+
+// Signs of every (scene, pair): the blocks of a scene are contiguous and
+// each (scene, pair) starts on a block boundary.
+__global__ void __launch_bounds__(256) k_signs_b(BatchArgs b) {
+    long long blk = blockIdx.x;
+    int si = last_le((const char*)&b.scenes[0].sign_blk0, sizeof(BScene), b.n_scenes, blk);
+    si = __builtin_amdgcn_readfirstlane(si);
+    const BScene& S = b.scenes[si];
+    long long nblk = (S.sc.d + 255) >> 8;
+    long long per_pair = (nblk + 255) >> 8;               // blocks per pair
+    long long local = blk - S.sign_blk0;
+    int pair = (int)(local / per_pair);
+    long long pblk = (local % per_pair) * 256 + threadIdx.x;
+    if (pblk >= nblk) return;
+    signs_block(b.seed, *b.step, (unsigned)pair, (unsigned)S.scene_index, pblk, S.sc.words,
+                S.bits + (long long)pair * S.sc.words);
+}
+
+// Setup of every (item, sign, triangle): each (item, sign) starts on a
+// block boundary.
+__global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
+    long long blk = blockIdx.x;
+    int it = last_le((const char*)&b.items[0].setup_blk0, sizeof(BItem), b.n_items, blk);
+    it = __builtin_amdgcn_readfirstlane(it);
+    const BItem& I = b.items[it];
+    const BScene& S = b.scenes[I.scene];
+    const DScene& sc = S.sc;
+    long long per_sign = ((long long)sc.n_tris + 255) >> 8;
+    long long local = blk - I.setup_blk0;
+    int s = (int)(local / per_sign);
+    int t = (int)((local % per_sign) * 256 + threadIdx.x);
+    if (t >= sc.n_tris) return;
+    const DView& vw = b.views[I.view];
+    int tiles = vw.tiles_x * vw.tiles_y;
+    setup_tri(sc, vw, S.theta, S.bits + (long long)I.pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t,
+              b.recR + I.rec_off + (long long)s * sc.n_tris, b.recS + I.rec_off + (long long)s * sc.n_tris,
+              b.counts + I.cnt_off + (long long)s * tiles, b.bins + I.bin_off + (long long)s * tiles * I.cap,
+              b.tile, I.cap);
+}
+
+// Persistent raster / shade / scatter: workgroups take (item, tile) units
+// from the queue until it is empty.
+template <int TILE>
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile_b(BatchArgs b) {
+    __shared__ TileShared<TILE, 0> S;
+    __shared__ unsigned long long next;
+    const float sgn2[2] = {1.0f, -1.0f};
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(b.work, 1ull);
+        __syncthreads();
+        long long w = (long long)next;
+        if (w >= b.total_tiles) break;
+        int it = last_le((const char*)&b.items[0].tile0, sizeof(BItem), b.n_items, w);
+        it = __builtin_amdgcn_readfirstlane(it);
+        const BItem& I = b.items[it];
+        const BScene& Sc = b.scenes[I.scene];
+        const DScene& sc = Sc.sc;
+        const DView& vw = b.views[I.view];
+        int tiles = vw.tiles_x * vw.tiles_y;
+        TileJob J;
+        J.sc = &sc;
+        J.vw = &vw;
+        J.theta = Sc.theta;
+        J.pb = Sc.bits + (long long)I.pair * sc.words;
+        J.eps = Sc.eps;
+        J.sgn[0] = sgn2[0];
+        J.sgn[1] = sgn2[1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            J.recR[s] = b.recR + I.rec_off + (long long)s * sc.n_tris;
+            J.recS[s] = b.recS + I.rec_off + (long long)s * sc.n_tris;
+            J.counts[s] = b.counts + I.cnt_off + (long long)s * tiles;
+            J.bins[s] = b.bins + I.bin_off + (long long)s * tiles * I.cap;
+        }
+        J.cap = I.cap;
+        J.tile = (int)(w - I.tile0);
+        J.stats = b.stats;
+        J.targets = Sc.targets + vw.tgt_off;
+        J.Rp = Sc.R + (long long)I.pair * sc.G;
+        J.K = Sc.K;
+        J.act_pos = Sc.act_pos;
+        J.any_act = Sc.any_act;
+        J.act_cls = Sc.act_cls;
+        J.out_rgb = nullptr;
+        J.out_id = nullptr;
+        J.out_uv = nullptr;
+        J.partial = nullptr;
+        tile_body<TILE, 0>(J, S);
+        __syncthreads();                 // table and keys are reused by the next unit
+    }
+}
+
+// Fold and step over the groups of every scene: each scene starts on a
+// block boundary.
+__global__ void __launch_bounds__(256) k_fold_b(BatchArgs b) {
+    long long blk = blockIdx.x;
+    int si = last_le((const char*)&b.scenes[0].group_blk0, sizeof(BScene), b.n_scenes, blk);
+    si = __builtin_amdgcn_readfirstlane(si);
+    const BScene& S = b.scenes[si];
+    long long g = (blk - S.group_blk0) * 256 + threadIdx.x;
+    if (g >= S.sc.G) return;
+    fold_group(S.sc, g, S.R, S.bits, b.n_pairs, S.eps, S.Q);
+}
+
+__global__ void __launch_bounds__(256) k_step_b(BatchArgs b) {
+    long long blk = blockIdx.x;
+    int si = last_le((const char*)&b.scenes[0].group_blk0, sizeof(BScene), b.n_scenes, blk);
+    si = __builtin_amdgcn_readfirstlane(si);
+    const BScene& S = b.scenes[si];
+    long long g = (blk - S.group_blk0) * 256 + threadIdx.x;
+    if (g >= S.sc.G) return;
+    unsigned t = *b.step;
+    if (t < 1u) t = 1u;                      // Adam steps count from 1
+    int ti = (int)min(t, (unsigned)b.n_bc) - 1;
+    step_group(S.sc, g, S.eps, S.lr, b.n_pairs, b.oc, b.bc1[ti], b.bc2[ti], 0, (float*)S.theta, S.m, S.v, S.Q,
+               S.K, nullptr, b.stats);
 }
 
 // --------------------------------------------------------- launchers --
@@ -630,4 +860,54 @@ hipError_t launch_step(hipStream_t st, const StepArgs& a) {
     dim3 grid((unsigned)((a.sc.G + 255) / 256));
     hipLaunchKernelGGL(k_step, grid, dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, st, b.work);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_signs_b, dim3((unsigned)b.sign_blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_setup_b, dim3((unsigned)b.setup_blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, int grid) {
+    int tb = (b.tile * b.tile > 256) ? 256 : b.tile * b.tile;
+    if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3((unsigned)grid), dim3(tb), 0, st, b);
+    else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3((unsigned)grid), dim3(tb), 0, st, b);
+    else hipLaunchKernelGGL(k_tile_b<32>, dim3((unsigned)grid), dim3(tb), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_fold_b, dim3((unsigned)b.group_blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_step_b, dim3((unsigned)b.group_blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, st, (unsigned*)b.step);
+    return hipGetLastError();
+}
+
+// Workgroups of the persistent tile kernel that fit on one CU.
+int batch_tile_blocks_per_cu(int tile) {
+    int n = 0;
+    int tb = (tile * tile > 256) ? 256 : tile * tile;
+    hipError_t e;
+    if (tile == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<8>, tb, 0);
+    else if (tile == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<16>, tb, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<32>, tb, 0);
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
 }

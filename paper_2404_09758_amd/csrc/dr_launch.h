@@ -4,6 +4,16 @@
 
 #include "dr_device.h"
 
+// Device counters (uint64 each).
+#define ST_OVERFLOWS 0
+#define ST_SATURATIONS 1
+#define ST_NONFINITE 2
+#define ST_BAD_INDEX 3
+#define ST_MAX_BIN 4
+#define ST_COUNT 8
+
+// ------------------------------------------------------- single scene --
+
 struct SetupArgs {
     DScene sc;
     DViews views;
@@ -11,7 +21,7 @@ struct SetupArgs {
     const float* theta;
     int n_views;            // views per pair (item -> pair = item / n_views)
     int item0;              // first item of this launch
-    int nsign;              // 1 (render) or 2 (+ and -)
+    int nsign;              // 1 (render, loss) or 2 (+ and -)
     float sgn[2];
     int tile;               // tile size in pixels
     int cap;                // bin capacity
@@ -37,7 +47,7 @@ struct TileArgs {
     const TriS* recS;
     unsigned* counts;
     const unsigned* bins;
-    unsigned long long* stats;       // [3]: overflows, saturations, nonfinite
+    unsigned long long* stats;
     // estimate mode
     const float* targets;
     long long* R;                    // [pairs, G] per-pair group sums
@@ -62,12 +72,18 @@ struct FoldArgs {
     long long* Q;
 };
 
+struct OptimConst {
+    int kind, averaging;
+    float b1, omb1, b2, omb2, eps_hat;
+};
+
 struct StepArgs {
     DScene sc;
     float eps[1 + DRD_MAX_TEX];
     float lr[1 + DRD_MAX_TEX];
-    int averaging, n_pairs, kind, decode_only;
-    float b1, omb1, b2, omb2, bc1, bc2, eps_hat;
+    int n_pairs, decode_only;
+    OptimConst oc;
+    float bc1, bc2;
     float* theta;
     float* m;
     float* v;
@@ -75,6 +91,68 @@ struct StepArgs {
     unsigned* K;
     float* grad;                 // decode-only output
     unsigned long long* stats;
+};
+
+// ------------------------------------------------------------- batch --
+//
+// A batch runs one optimisation step of many independent scenes with one
+// launch per kernel: every (scene, pair, view) item's tiles are served to a
+// persistent raster/scatter kernel from a work counter.  All descriptors
+// live in device memory and are fixed when the batch is created; the step
+// number is read from a device counter, so the step can be captured once
+// as a graph and replayed.
+
+struct BScene {
+    DScene sc;
+    const float* theta;          // caller [d]
+    float* m;
+    float* v;
+    long long* Q;                // caller [d]
+    unsigned* K;                 // caller [G]
+    uint32_t* bits;              // scratch [pairs, words]
+    long long* R;                // scratch [pairs, G]
+    const float* targets;        // caller: the scene's views, concatenated
+    float eps[1 + DRD_MAX_TEX];
+    float lr[1 + DRD_MAX_TEX];
+    int act_pos, any_act;
+    int act_cls[DRD_MAX_TEX];
+    int n_views, view0;          // views [view0, view0 + n_views) of the view table
+    int scene_index;             // counter word 3 of the signs
+    long long sign_blk0;         // first block of this scene in the signs launch
+    long long group_blk0;        // first block of this scene in the fold / step launches
+};
+
+struct BItem {
+    int scene, pair, view;       // view: index in the batch view table
+    int cap;                     // bin capacity
+    long long rec_off;           // records of sign 0 (sign 1 at + n_tris)
+    long long cnt_off;           // bin counters of sign 0 (sign 1 at + tiles)
+    long long bin_off;           // bin entries of sign 0 (sign 1 at + tiles * cap)
+    long long setup_blk0;        // first block of this item in the setup launch
+    long long tile0;             // first work unit of this item in the tile queue
+};
+
+struct BatchArgs {
+    const BScene* scenes;
+    int n_scenes;
+    const DView* views;
+    const BItem* items;
+    int n_items;
+    int n_pairs;
+    unsigned long long seed;
+    const unsigned* step;        // device step counter (1-based)
+    long long sign_blocks, setup_blocks, group_blocks, total_tiles;
+    unsigned long long* work;    // tile queue counter
+    TriR* recR;
+    TriS* recS;
+    unsigned* counts;
+    unsigned* bins;
+    unsigned long long* stats;
+    OptimConst oc;
+    const float* bc1;            // Adam bias corrections by step, [n_bc]
+    const float* bc2;
+    int n_bc;
+    int tile;
 };
 
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
@@ -86,3 +164,12 @@ hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tile
 hipError_t launch_check_tri(hipStream_t st, const int* tri, long long n, int n_verts, unsigned long long* bad);
 hipError_t launch_fold(hipStream_t st, const FoldArgs& a);
 hipError_t launch_step(hipStream_t st, const StepArgs& a);
+
+hipError_t launch_batch_begin(hipStream_t st, const BatchArgs& b);
+hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b);
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, int grid);
+hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b);
+hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b);
+hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b);
+int batch_tile_blocks_per_cu(int tile);

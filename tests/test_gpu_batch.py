@@ -1,0 +1,101 @@
+"""Batching form (dr_batch_*): many scenes of uneven size per launch, the
+step captured as a HIP graph.  Every scene's Q, K and parameters must equal
+those of the plain path (and the oracle) bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2404_09758_amd import api, batch
+from paper_2404_09758_amd import scenes as S
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+SPECS = [  # freq, splits, (W, H), texture shape, views
+    (3, 0, (64, 48), (32, 32, 3), 1),
+    (6, 0, (96, 80), (48, 48, 3), 2),
+    (2, 0, (40, 40), (16, 16, 3), 1),
+    (4, 1, (120, 90), (64, 32, 3), 1),
+    (4, 0, (70, 100), (24, 24, 3), 2),
+]
+
+
+def make_scenes():
+    out = []
+    for i, (f, sp, res, ts, nv) in enumerate(SPECS):
+        sc = H.sphere_scene(f, sp, res=res, shading=S.SHADING_LAMBERT, tex_shapes=(ts,), seed=10 + i, views=nv)
+        sc.lr = [2e-3, 5e-3]
+        out.append(sc)
+    return out
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_batch_estimate_matches_oracle_and_plain(tile):
+    scs = make_scenes()
+    seed, step, pairs = 99, 5, 2
+    targets = []
+    for sc in scs:
+        o = oracle.Oracle(sc)
+        targets.append([o.render(sc.flat_params(True), v)[0] for v in sc.views])
+    bt = batch.Batch(scs, pairs, DEV, tile_px=tile, seed=seed, first_step=step,
+                     targets=[[torch.tensor(t, device=DEV) for t in tg] for tg in targets])
+    bt.estimate()
+    for b, sc in enumerate(scs):
+        o = oracle.Oracle(sc)
+        Qo, Ko, _, _ = o.estimate(sc.flat_params(), sc.views, targets[b], seed, step, pairs, sc.eps, scene_index=b)
+        assert np.array_equal(host(bt.K[b]).view(np.uint32), Ko), f"scene {b}"
+        assert np.array_equal(host(bt.Q[b]), Qo), f"scene {b}"
+        ctx = api.Context(sc, DEV, tuning=(tile, 256, 1))
+        ctx.set_scene_index(b)
+        Q, K = ctx.estimate_grad(bt.theta[b], sc.views, bt.targets[b], seed, step, pairs, sc.eps)
+        assert torch.equal(Q, bt.Q[b]) and torch.equal(K, bt.K[b])
+    assert bt.get_step() == step          # estimate alone does not advance the step
+
+
+def test_batch_graph_replays_match_eager_plain_steps():
+    scs = make_scenes()
+    seed, pairs = 7, 2
+    bt = batch.Batch(scs, pairs, DEV, tile_px=16, seed=seed, first_step=1)
+    # the plain path on copies of the same state
+    ctxs, th, m, v = [], [], [], []
+    for b, sc in enumerate(scs):
+        c = api.Context(sc, DEV, tuning=(16, 256, 1))
+        c.set_scene_index(b)
+        ctxs.append(c)
+        th.append(bt.theta[b].clone())
+        m.append(bt.m[b].clone())
+        v.append(bt.v[b].clone())
+    for t in range(1, 4):
+        bt.step(use_graph=True)
+        # eager work between replays
+        for b, sc in enumerate(scs):
+            Q, K = ctxs[b].estimate_grad(th[b], sc.views, bt.targets[b], seed, t, pairs, sc.eps)
+            ctxs[b].step(th[b], m[b], v[b], t, Q, K, sc.eps, pairs, kind=api.ADAM, averaging=api.AVG_COUNT,
+                         lr=sc.lr)
+        torch.cuda.synchronize()
+        for b in range(len(scs)):
+            assert torch.equal(bt.theta[b], th[b]), f"replay {t}, scene {b}"
+            assert torch.equal(bt.m[b], m[b]) and torch.equal(bt.v[b], v[b])
+            assert not bt.Q[b].any() and not bt.K[b].any()
+        assert bt.get_step() == t + 1
+
+
+def test_batch_graph_equals_direct_launches():
+    scs = make_scenes()
+    a = batch.Batch(scs, 3, DEV, tile_px=16, seed=3, first_step=4, kind=api.SGD)
+    b = batch.Batch(scs, 3, DEV, tile_px=32, seed=3, first_step=4, kind=api.SGD)
+    for _ in range(2):
+        a.step(use_graph=True)
+        b.step(use_graph=False)
+    torch.cuda.synchronize()
+    for i in range(len(scs)):
+        assert torch.equal(a.theta[i], b.theta[i])
+    st = a.stats()
+    assert st["max_bin"] > 0 and st["tile_overflows"] == 0

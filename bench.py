@@ -51,10 +51,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny"])
+    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny", "batch64"])
     ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", default="both", choices=["both", "batched", "plain"])
+    ap.add_argument("--mode", default="both", choices=["both", "graph", "batched", "plain"])
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the run, copy a float32 buffer of this many MiB 3 times (a kernel of "
                          "known traffic, to calibrate profiler byte counters)")
@@ -131,6 +131,69 @@ def cpu_baseline(sc, n_items):
                       f"step, single-threaded, extrapolated to a whole step ({sec_per_step:.1f} s/step)"}
 
 
+def run_graph_mode(sc_list, tg_list, steps, warmup, api, batch_mod, torch, dev, tile=16, caps=None):
+    """The batching form: every scene's step as one launch per kernel,
+    captured once as a HIP graph and replayed."""
+    bt = batch_mod.Batch(sc_list, sc_list[0].n_pairs, dev, tile_px=tile, seed=sc_list[0].seed, first_step=1,
+                         targets=tg_list, kind=api.ADAM, averaging=api.AVG_COUNT, bin_capacities=caps)
+    for _ in range(warmup):
+        bt.step(use_graph=True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        bt.step(use_graph=True)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ev_ms = start.elapsed_time(stop)
+    # per-kernel durations: the same kernels launched directly, with events
+    bt.timing_read(reset=True)
+    bt.timing_enable(True)
+    for _ in range(steps):
+        bt.step(use_graph=False)
+    bt.timing_enable(False)
+    tm = bt.timing_read(reset=True)
+    st = bt.stats()
+    return {"ms_per_step": ev_ms / steps, "wall_ms_per_step": 1e3 * wall / steps, "timing": tm,
+            "stats": st, "batch": bt}
+
+
+def run_sequential_plain(sc_list, tg_list, steps, warmup, api, torch, dev, tile=16, caps=None):
+    """Each scene stepped on its own with one raster launch per item."""
+    ctxs, th, m, v = [], [], [], []
+    for b, sc in enumerate(sc_list):
+        c = api.Context(sc, dev, tuning=(tile, 256 if caps is None else caps[b], 1))
+        c.set_scene_index(b)
+        ctxs.append(c)
+        th.append(torch.tensor(sc.flat_params(), device=dev))
+        m.append(torch.zeros_like(th[-1]))
+        v.append(torch.zeros_like(th[-1]))
+    t = 0
+
+    def one_step():
+        nonlocal t
+        t += 1
+        for b, sc in enumerate(sc_list):
+            Q, K = ctxs[b].estimate_grad(th[b], sc.views, tg_list[b], sc.seed, t, sc.n_pairs, sc.eps)
+            ctxs[b].step(th[b], m[b], v[b], t, Q, K, sc.eps, sc.n_pairs, kind=api.ADAM, averaging=api.AVG_COUNT,
+                         lr=sc.lr)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        one_step()
+    stop.record()
+    torch.cuda.synchronize()
+    return {"ms_per_step": start.elapsed_time(stop) / steps}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -138,20 +201,28 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_2404_09758_amd import api, scenes
-    sc = scenes.CONFIGS[args.config]()
+    from paper_2404_09758_amd import api, autotune, batch, scenes
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.config == "batch64":
+        return main_batch64(args, torch, api, autotune, batch, scenes, dev)
+    sc = scenes.CONFIGS[args.config]()
     ctx = api.Context(sc, dev, tuning=(16, 256, 0))
     th0 = torch.tensor(sc.flat_params(), device=dev)
     tgt_th = torch.tensor(sc.flat_params(True), device=dev)
     tg = torch.cat([ctx.render(tgt_th, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views])
     eps = sc.eps
     px_per_step = sc.n_pairs * sum(v.width * v.height for v in sc.views)
+    # launch shape from the autotuner (untimed)
+    (tile, cap, _), tune_report = autotune.tune_scene(ctx, th0, sc.views, tg, sc.n_pairs, eps)
     results = {}
-    modes = {"batched": (16, 256, 0), "plain": (16, 256, 1)}
-    order = ["batched", "plain"] if args.mode == "both" else [args.mode]
+    modes = {"batched": (tile, cap, 0), "plain": (tile, cap, 1)}
+    order = ["graph", "batched", "plain"] if args.mode == "both" else [args.mode]
     for name in order:
+        if name == "graph":
+            results[name] = run_graph_mode([sc], [tg], args.steps, args.warmup, api, batch, torch, dev, tile=tile,
+                                           caps=[cap])
+            continue
         th = th0.clone()
         m = torch.zeros_like(th)
         v = torch.zeros_like(th)
@@ -162,8 +233,9 @@ def main():
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     launches_per_step = tm["tile_launches"] / args.steps
     alg_bytes_launch = BYTES_PER_PIXEL_ESTIMATE * px_per_step / launches_per_step
-    traffic = measured_traffic() if main_mode == "batched" and args.config == "paper" else None
+    traffic = measured_traffic() if main_mode == "graph" and args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
+    kernel = f"k_tile_b<{tile}>" if main_mode == "graph" else f"k_tile<{tile},0>"
     out = {
         "metric": METRIC,
         "value": 1e3 / r["ms_per_step"],
@@ -180,13 +252,13 @@ def main():
         "config": {"workload": f"{args.config}: {sc.views[0].width}x{sc.views[0].height} px, "
                                f"{sc.n_tris} tris, {len(sc.views)} views x {sc.n_pairs} pairs, "
                                f"d={sc.n_params}, {['unlit', 'lambert', 'ggx'][sc.shading]}",
-                   "mode": main_mode, "tile_px": 16, "bin_capacity": 256,
+                   "mode": main_mode, "tile_px": tile, "bin_capacity": cap,
                    "pixel_estimates_per_step": px_per_step},
+        "autotune": {str(k): v for k, v in tune_report.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_tile", "kernel_avg_ms": tile_avg_ms,
+                     "kernel": kernel, "kernel_avg_ms": tile_avg_ms,
                      "alg_bytes_per_launch": alg_bytes_launch},
-        "contributions_per_step": r["contributions_per_step"],
         "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")},
         "pixel_estimates_per_s": px_per_step * 1e3 / r["ms_per_step"],
     }
@@ -202,6 +274,47 @@ def main():
         out["copy_probe_bytes"] = 4 * n
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_items)
+    print(json.dumps(out), flush=True)
+
+
+def main_batch64(args, torch, api, autotune, batch, scenes, dev):
+    """64 independent scenes of uneven size: one graph-captured batched step
+    against 64 sequential plain steps (equal results, bit for bit)."""
+    n = 64
+    scs = [scenes.make_batch_scene(b) for b in range(n)]
+    tgs = []
+    for sc in scs:
+        c = api.Context(sc, dev)
+        tt = torch.tensor(sc.flat_params(True), device=dev)
+        tgs.append(torch.cat([c.render(tt, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views]))
+        del c
+    px = sum(sc.n_pairs * sum(v.width * v.height for v in sc.views) for sc in scs)
+    tile, caps, tune_report = autotune.tune_batch(scs, tgs, scs[0].n_pairs, dev, seed=scs[0].seed)
+    g = run_graph_mode(scs, tgs, args.steps, args.warmup, api, batch, torch, dev, tile=tile, caps=caps)
+    p = run_sequential_plain(scs, tgs, args.steps, args.warmup, api, torch, dev, tile=tile, caps=caps)
+    tm = g["timing"]
+    tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
+    alg = BYTES_PER_PIXEL_ESTIMATE * px / (tm["tile_launches"] / args.steps)
+    achieved = alg / (tile_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": 1e3 / g["ms_per_step"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch64: {n} scenes, F in [{min(s.n_tris for s in scs)}, "
+                               f"{max(s.n_tris for s in scs)}], 4 pairs x 1 view each, lambert, "
+                               f"{px} pixel-estimates per step", "mode": "graph", "tile_px": tile,
+                   "bin_capacity_max": max(caps)},
+        "autotune": {str(k): v for k, v in tune_report.items()},
+        "stats": g["stats"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_tile_b<{tile}>",
+                     "kernel_avg_ms": tile_avg_ms, "alg_bytes_per_launch": alg},
+        "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")},
+        "graph_steps_per_s": 1e3 / g["ms_per_step"],
+        "sequential_plain_steps_per_s": 1e3 / p["ms_per_step"],
+        "speedup_vs_sequential_plain": p["ms_per_step"] / g["ms_per_step"],
+        "pixel_estimates_per_s": px * 1e3 / g["ms_per_step"],
+    }
     print(json.dumps(out), flush=True)
 
 

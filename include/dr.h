@@ -202,8 +202,8 @@ dr_status dr_reset_stats(dr_ctx* ctx);
 /* ---------------------------------------------------------------- batch
  * The batching form: one optimisation step of many independent scenes of
  * uneven size, each with n_pairs antithetic pairs over its views, run with
- * one launch per kernel -- a persistent raster/shade/scatter kernel serves
- * every (scene, pair, view, tile) unit from a work queue -- followed by one
+ * one launch per kernel -- one raster/shade/scatter launch covers every
+ * (scene, pair, view, tile) unit, costliest scenes first -- followed by one
  * Adam/SGD launch over all scenes' parameters.  The step number lives on
  * the device and advances with each step, so the whole step can be captured
  * once as a HIP graph and replayed.  Scene b draws its signs with counter
@@ -240,6 +240,9 @@ dr_status dr_batch_step(dr_batch* b, int use_graph);
 dr_status dr_batch_set_step(dr_batch* b, uint32_t step);      /* synchronous; step >= 1 */
 dr_status dr_batch_get_step(dr_batch* b, uint32_t* step);     /* synchronous */
 dr_status dr_batch_stats(dr_batch* b, dr_stats_t* out);       /* synchronous */
+/* Per-kernel timing of direct (not graph-replayed) launches, as dr_timing_*. */
+dr_status dr_batch_timing_enable(dr_batch* b, int enable);
+dr_status dr_batch_timing_read(dr_batch* b, dr_timing_t* out, int reset);
 const char* dr_batch_last_error(const dr_batch* b);
 
 const char* dr_status_str(dr_status s);

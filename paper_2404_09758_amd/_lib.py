@@ -96,6 +96,8 @@ SIGNATURES = {
     "dr_batch_set_step": (C.c_int, [_vp, C.c_uint32]),
     "dr_batch_get_step": (C.c_int, [_vp, C.POINTER(C.c_uint32)]),
     "dr_batch_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
+    "dr_batch_timing_enable": (C.c_int, [_vp, C.c_int]),
+    "dr_batch_timing_read": (C.c_int, [_vp, C.POINTER(Timing), C.c_int]),
     "dr_batch_last_error": (C.c_char_p, [_vp]),
     "dr_status_str": (C.c_char_p, [C.c_int]),
     "dr_last_error": (C.c_char_p, [_vp]),

@@ -112,6 +112,14 @@ class Batch:
         self._call("dr_batch_get_step", C.byref(t))
         return int(t.value)
 
+    def timing_enable(self, on=True):
+        self._call("dr_batch_timing_enable", int(bool(on)))
+
+    def timing_read(self, reset=True):
+        t = L.Timing()
+        self._call("dr_batch_timing_read", C.byref(t), int(bool(reset)))
+        return {k: getattr(t, k) for k, _ in L.Timing._fields_}
+
     def stats(self):
         s = L.Stats()
         self._call("dr_batch_stats", C.byref(s))

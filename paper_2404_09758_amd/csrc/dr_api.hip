@@ -15,6 +15,78 @@
 #include "dr.h"
 #include "dr_launch.h"
 
+enum { K_SIGNS = 0, K_SETUP = 1, K_TILE = 2, K_FOLD = 3, K_STEP = 4 };
+
+// Event pairs recorded around launches while enabled.
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> free_;
+    std::vector<hipEvent_t> pending[5][2];        // [kind][begin/end]
+
+    hipEvent_t take() {
+        if (!free_.empty()) {
+            hipEvent_t e = free_.back();
+            free_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    // Runs one launch on stream st, bracketed by events when enabled.
+    template <typename F>
+    hipError_t run(hipStream_t st, int kind, F launch) {
+        if (!on) return launch();
+        hipEvent_t b = take(), e = take();
+        if (!b || !e) return hipErrorOutOfMemory;
+        hipError_t r = hipEventRecord(b, st);
+        if (r != hipSuccess) return r;
+        r = launch();
+        if (r != hipSuccess) return r;
+        r = hipEventRecord(e, st);
+        pending[kind][0].push_back(b);
+        pending[kind][1].push_back(e);
+        return r;
+    }
+
+    // Sums the durations (the stream must be synchronised).
+    hipError_t read(dr_timing_t* out, bool reset) {
+        double ms[5] = {0, 0, 0, 0, 0};
+        int64_t n[5] = {0, 0, 0, 0, 0};
+        for (int k = 0; k < 5; ++k) {
+            for (size_t i = 0; i < pending[k][0].size(); ++i) {
+                float t = 0.0f;
+                hipError_t r = hipEventElapsedTime(&t, pending[k][0][i], pending[k][1][i]);
+                if (r != hipSuccess) return r;
+                ms[k] += t;
+                n[k] += 1;
+            }
+            if (reset)
+                for (int j = 0; j < 2; ++j) {
+                    for (hipEvent_t e : pending[k][j]) free_.push_back(e);
+                    pending[k][j].clear();
+                }
+        }
+        out->signs_ms = ms[K_SIGNS]; out->signs_launches = n[K_SIGNS];
+        out->setup_ms = ms[K_SETUP]; out->setup_launches = n[K_SETUP];
+        out->tile_ms = ms[K_TILE]; out->tile_launches = n[K_TILE];
+        out->fold_ms = ms[K_FOLD]; out->fold_launches = n[K_FOLD];
+        out->step_ms = ms[K_STEP]; out->step_launches = n[K_STEP];
+        return hipSuccess;
+    }
+
+    void destroy() {
+        for (int k = 0; k < 5; ++k)
+            for (int j = 0; j < 2; ++j) {
+                for (hipEvent_t e : pending[k][j]) (void)hipEventDestroy(e);
+                pending[k][j].clear();
+            }
+        for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+        free_.clear();
+    }
+};
+
 struct dr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -25,6 +97,7 @@ struct dr_ctx {
     std::string err;
     TriR* recR = nullptr;
     TriS* recS = nullptr;
+    TriF* recF = nullptr;
     long long rec_slots = 0;
     unsigned* counts = nullptr;
     unsigned* bins = nullptr;
@@ -37,40 +110,8 @@ struct dr_ctx {
     double* partials = nullptr;
     long long partial_slots = 0;
     unsigned long long* stats = nullptr;
-    // timing: event pairs recorded around launches while enabled
-    bool timing = false;
-    std::vector<hipEvent_t> ev_free;
-    std::vector<hipEvent_t> ev_pending[5][2];     // [kind][begin/end]
+    Timer timer;
 };
-
-enum { K_SIGNS = 0, K_SETUP = 1, K_TILE = 2, K_FOLD = 3, K_STEP = 4 };
-
-static hipEvent_t take_event(dr_ctx* c) {
-    if (!c->ev_free.empty()) {
-        hipEvent_t e = c->ev_free.back();
-        c->ev_free.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Runs one launch, bracketed by events when timing is enabled.
-template <typename F>
-static hipError_t timed(dr_ctx* c, int kind, F launch) {
-    if (!c->timing) return launch();
-    hipEvent_t b = take_event(c), e = take_event(c);
-    if (!b || !e) return hipErrorOutOfMemory;
-    hipError_t r = hipEventRecord(b, c->stream);
-    if (r != hipSuccess) return r;
-    r = launch();
-    if (r != hipSuccess) return r;
-    r = hipEventRecord(e, c->stream);
-    c->ev_pending[kind][0].push_back(b);
-    c->ev_pending[kind][1].push_back(e);
-    return r;
-}
 
 static dr_status fail(dr_ctx* c, dr_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -121,6 +162,9 @@ static dr_status ensure_raster(dr_ctx* c, long long slots, int max_tiles) {
     if (s) return s;
     have = c->rec_slots;
     s = grow(c, &c->recS, &have, slots * c->sc.n_tris, sizeof(TriS), false);
+    if (s) return s;
+    have = c->rec_slots;
+    s = grow(c, &c->recF, &have, slots * c->sc.n_tris, sizeof(TriF), false);
     if (s) return s;
     if (slots * c->sc.n_tris > c->rec_slots) c->rec_slots = slots * c->sc.n_tris;
     s = grow(c, &c->counts, &c->tile_slots, slots * (long long)max_tiles, sizeof(unsigned), true);
@@ -283,13 +327,10 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
 extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats, c->partials};
+    void* ptrs[] = {c->recR, c->recS, c->recF, c->counts, c->bins, c->R, c->bits, c->stats, c->partials};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    for (int k = 0; k < 5; ++k)
-        for (int j = 0; j < 2; ++j)
-            for (hipEvent_t e : c->ev_pending[k][j]) (void)hipEventDestroy(e);
-    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    c->timer.destroy();
     delete c;
     return DR_OK;
 }
@@ -336,7 +377,7 @@ extern "C" dr_status dr_signs(dr_ctx* c, uint64_t seed, uint32_t step, uint32_t 
     if (!bits) return fail(c, DR_E_INVALID, "bits is NULL");
     dr_status s = device_guard(c);
     if (s) return s;
-    HIPCHK(c, timed(c, K_SIGNS, [&] { return launch_signs(c->stream, seed, step, pair, scene, c->sc.d, c->sc.words, 1, bits); }));
+    HIPCHK(c, c->timer.run(c->stream, K_SIGNS, [&] { return launch_signs(c->stream, seed, step, pair, scene, c->sc.d, c->sc.words, 1, bits); }));
     return DR_OK;
 }
 
@@ -367,7 +408,7 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     if (pert) {
         s = ensure_bits(c, 1);
         if (s) return s;
-        HIPCHK(c, timed(c, K_SIGNS, [&] {
+        HIPCHK(c, c->timer.run(c->stream, K_SIGNS, [&] {
             return launch_signs(c->stream, pert->seed, pert->step, pert->pair, pert->scene_index, c->sc.d,
                                 c->sc.words, 1, c->bits);
         }));
@@ -391,9 +432,10 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
+    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
-    HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, 1); }));
+    HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, 1); }));
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
     ta.sc = c->sc;
@@ -409,13 +451,14 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
+    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
     ta.out_rgb = rgb;
     ta.out_id = id;
     ta.out_uv = uv;
-    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 1, 1, max_tiles); }));
+    HIPCHK(c, c->timer.run(c->stream, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 1, 1, max_tiles); }));
     return DR_OK;
 }
 
@@ -457,7 +500,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     DPert dp;
     dp.bits = c->bits;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = (b < 1 + c->sc.n_tex) ? eps[b] : 0.0f;
-    HIPCHK(c, timed(c, K_SIGNS, [&] {
+    HIPCHK(c, c->timer.run(c->stream, K_SIGNS, [&] {
         return launch_signs(c->stream, seed, step, 0u, c->scene_index, c->sc.d, c->sc.words, n_pairs, c->bits);
     }));
 
@@ -476,6 +519,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
+    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
     TileArgs ta;
@@ -492,6 +536,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
+    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
@@ -509,8 +554,8 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
         int n = (int)std::min(per, items - i0);
         sa.item0 = (int)i0;
         ta.item0 = (int)i0;
-        HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
-        HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 0, n, max_tiles); }));
+        HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
+        HIPCHK(c, c->timer.run(c->stream, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 0, n, max_tiles); }));
     }
     FoldArgs fa;
     std::memset(&fa, 0, sizeof(fa));
@@ -520,7 +565,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     fa.n_pairs = n_pairs;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) fa.eps[b] = dp.eps[b];
     fa.Q = (long long*)Q;
-    HIPCHK(c, timed(c, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
     return DR_OK;
 }
 
@@ -567,9 +612,10 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
+    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
-    HIPCHK(c, timed(c, K_SETUP, [&] { return launch_setup(c->stream, sa, n_views); }));
+    HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n_views); }));
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
     ta.sc = c->sc;
@@ -584,12 +630,13 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
+    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
     ta.targets = targets;
     ta.partials = c->partials;
-    HIPCHK(c, timed(c, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 2, n_views, max_tiles); }));
+    HIPCHK(c, c->timer.run(c->stream, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 2, n_views, max_tiles); }));
     HIPCHK(c, launch_sum_tiles(c->stream, c->partials, max_tiles, dv, n_views, loss));
     return DR_OK;
 }
@@ -640,7 +687,7 @@ static dr_status step_common(dr_ctx* c, float* theta, float* m, float* v, uint32
         a.m = m;
         a.v = v;
     }
-    HIPCHK(c, timed(c, K_STEP, [&] { return launch_step(c->stream, a); }));
+    HIPCHK(c, c->timer.run(c->stream, K_STEP, [&] { return launch_step(c->stream, a); }));
     return DR_OK;
 }
 
@@ -673,7 +720,7 @@ extern "C" dr_status dr_step(dr_ctx* c, float* theta, float* m, float* v, uint32
 
 extern "C" dr_status dr_timing_enable(dr_ctx* c, int enable) {
     if (!c) return DR_E_INVALID;
-    c->timing = enable != 0;
+    c->timer.on = enable != 0;
     return DR_OK;
 }
 
@@ -682,27 +729,7 @@ extern "C" dr_status dr_timing_read(dr_ctx* c, dr_timing_t* out, int reset) {
     dr_status s = device_guard(c);
     if (s) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms[5] = {0, 0, 0, 0, 0};
-    int64_t n[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < 5; ++k) {
-        for (size_t i = 0; i < c->ev_pending[k][0].size(); ++i) {
-            float t = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&t, c->ev_pending[k][0][i], c->ev_pending[k][1][i]));
-            ms[k] += t;
-            n[k] += 1;
-        }
-        if (reset) {
-            for (int j = 0; j < 2; ++j) {
-                for (hipEvent_t e : c->ev_pending[k][j]) c->ev_free.push_back(e);
-                c->ev_pending[k][j].clear();
-            }
-        }
-    }
-    out->signs_ms = ms[K_SIGNS]; out->signs_launches = n[K_SIGNS];
-    out->setup_ms = ms[K_SETUP]; out->setup_launches = n[K_SETUP];
-    out->tile_ms = ms[K_TILE]; out->tile_launches = n[K_TILE];
-    out->fold_ms = ms[K_FOLD]; out->fold_launches = n[K_FOLD];
-    out->step_ms = ms[K_STEP]; out->step_launches = n[K_STEP];
+    HIPCHK(c, c->timer.read(out, reset != 0));
     return DR_OK;
 }
 
@@ -754,11 +781,11 @@ struct dr_batch {
     hipGraphExec_t exec = nullptr;
     std::string err;
     BatchArgs args{};
-    int grid = 0;                      // persistent tile kernel workgroups
     int n_scenes = 0;
     // device allocations
     std::vector<void*> allocs;
     unsigned long long* stats = nullptr;
+    Timer timer;                       // direct launches only (not graph replays)
 };
 
 static dr_status bfail(dr_batch* b, dr_status s, const std::string& msg) {
@@ -774,6 +801,7 @@ static dr_status bfail(dr_batch* b, dr_status s, const std::string& msg) {
     } while (0)
 
 static void batch_free(dr_batch* b) {
+    b->timer.destroy();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
@@ -845,7 +873,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     std::vector<BItem> hi;
     std::vector<int> order(n_scenes);
     for (int i = 0; i < n_scenes; ++i) order[i] = i;
-    // items of the costliest scenes first, so the queue ends on small units
+    // items of the costliest scenes first, so the launch ends on small units
     auto cost = [&](int i) {
         long long px = 0;
         for (int v = 0; v < scenes[i].n_views; ++v) px += (long long)scenes[i].views[v].width * scenes[i].views[v].height;
@@ -923,7 +951,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
                 hi.push_back(I);
             }
     }
-    if (sign_blk > 0x7fffffffll || setup_blk > 0x7fffffffll || group_blk > 0x7fffffffll) {
+    if (sign_blk > 0x7fffffffll || setup_blk > 0x7fffffffll || group_blk > 0x7fffffffll || tile0 > 0x7fffffffll) {
         batch_free(b);
         delete b;
         return DR_E_UNSUPPORTED;
@@ -952,14 +980,14 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     BItem* dit = nullptr;
     float *dbc1 = nullptr, *dbc2 = nullptr;
     unsigned* dstep = nullptr;
-    unsigned long long* work = nullptr;
     if ((st = balloc(b, &bits, (size_t)bits_total, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
         (st = balloc(b, &A.recR, (size_t)rec, false)) || (st = balloc(b, &A.recS, (size_t)rec, false)) ||
+        (st = balloc(b, &A.recF, (size_t)rec, false)) ||
         (st = balloc(b, &A.counts, (size_t)cnt, true)) || (st = balloc(b, &A.bins, (size_t)bin, false)) ||
         (st = balloc(b, &dsc, hs.size(), false)) || (st = balloc(b, &dvw, hv.size(), false)) ||
         (st = balloc(b, &dit, hi.size(), false)) || (st = balloc(b, &dbc1, bc1.size(), false)) ||
         (st = balloc(b, &dbc2, bc2.size(), false)) || (st = balloc(b, &dstep, 1, false)) ||
-        (st = balloc(b, &work, 1, true)) || (st = balloc(b, &b->stats, ST_COUNT, true))) {
+        (st = balloc(b, &b->stats, ST_COUNT, true))) {
         batch_free(b);
         delete b;
         return st;
@@ -985,11 +1013,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     A.bc1 = dbc1;
     A.bc2 = dbc2;
     A.step = dstep;
-    A.work = work;
     A.stats = b->stats;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    b->grid = cus * batch_tile_blocks_per_cu(tile_px);
     *out = b;
     return DR_OK;
 }
@@ -1003,16 +1027,17 @@ extern "C" dr_status dr_batch_destroy(dr_batch* b) {
     return DR_OK;
 }
 
-static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend) {
+static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool timed) {
     const BatchArgs& A = b->args;
+    Timer off;
+    Timer& T = timed ? b->timer : off;
     hipError_t e;
-    if ((e = launch_batch_begin(st, A)) != hipSuccess) return e;
-    if ((e = launch_batch_signs(st, A)) != hipSuccess) return e;
-    if ((e = launch_batch_setup(st, A)) != hipSuccess) return e;
-    if ((e = launch_batch_tile(st, A, b->grid)) != hipSuccess) return e;
-    if ((e = launch_batch_fold(st, A)) != hipSuccess) return e;
+    if ((e = T.run(st, K_SIGNS, [&] { return launch_batch_signs(st, A); })) != hipSuccess) return e;
+    if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A); })) != hipSuccess) return e;
+    if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A); })) != hipSuccess) return e;
+    if ((e = T.run(st, K_FOLD, [&] { return launch_batch_fold(st, A); })) != hipSuccess) return e;
     if (descend) {
-        if ((e = launch_batch_step(st, A)) != hipSuccess) return e;
+        if ((e = T.run(st, K_STEP, [&] { return launch_batch_step(st, A); })) != hipSuccess) return e;
         if ((e = launch_batch_end(st, A)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1029,7 +1054,7 @@ extern "C" dr_status dr_batch_estimate(dr_batch* b) {
     if (!b) return DR_E_INVALID;
     dr_status s = batch_device(b);
     if (s) return s;
-    BHIPCHK(b, batch_enqueue(b, b->stream, false));
+    BHIPCHK(b, batch_enqueue(b, b->stream, false, true));
     return DR_OK;
 }
 
@@ -1038,7 +1063,7 @@ extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
     dr_status s = batch_device(b);
     if (s) return s;
     if (!use_graph) {
-        BHIPCHK(b, batch_enqueue(b, b->stream, true));
+        BHIPCHK(b, batch_enqueue(b, b->stream, true, true));
         return DR_OK;
     }
     if (!b->exec) {
@@ -1049,7 +1074,7 @@ extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
         BHIPCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
         BHIPCHK(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
         BHIPCHK(b, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = batch_enqueue(b, b->gstream, true);
+        hipError_t e = batch_enqueue(b, b->gstream, true, false);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->gstream, &g);
         if (e != hipSuccess || e2 != hipSuccess)
@@ -1098,6 +1123,21 @@ extern "C" dr_status dr_batch_stats(dr_batch* b, dr_stats_t* out) {
     out->saturations = h[ST_SATURATIONS];
     out->nonfinite = h[ST_NONFINITE];
     out->max_bin = h[ST_MAX_BIN];
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_timing_enable(dr_batch* b, int enable) {
+    if (!b) return DR_E_INVALID;
+    b->timer.on = enable != 0;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_batch_timing_read(dr_batch* b, dr_timing_t* out, int reset) {
+    if (!b || !out) return DR_E_INVALID;
+    dr_status s = batch_device(b);
+    if (s) return s;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    BHIPCHK(b, b->timer.read(out, reset != 0));
     return DR_OK;
 }
 

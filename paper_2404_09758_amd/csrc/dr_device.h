@@ -75,11 +75,22 @@ struct __align__(16) TriS {
     int pad;
 };
 
+// Per-face shading frame (64 B), computed once per triangle by the setup:
+// the unit face normal and (GGX) the tangent frame of the face's UV map.
+struct __align__(16) TriF {
+    float nf[3];
+    float T[3];
+    float B[3];
+    int pad[7];
+};
+
 static_assert(sizeof(TriR) == 64, "TriR layout");
 static_assert(sizeof(TriS) == 64, "TriS layout");
+static_assert(sizeof(TriF) == 64, "TriF layout");
 
 #define TRI_VALID 1u
 #define TRI_SWAPPED 16u
+#define TRI_SMALL 32u          // bbox spans < 2^15 subpixels: 32-bit edge functions are exact
 
 // ---------------------------------------------------------------- signs --
 
@@ -160,6 +171,18 @@ __device__ __forceinline__ bool inside(const TriR& r, int px, int py, long long&
     return ok0 && ok1 && ok2;
 }
 
+// The same coverage test for triangles flagged TRI_SMALL: every product is
+// below 2^30 in magnitude, so 24-bit multiplies give the exact values.
+__device__ __forceinline__ bool inside_small(const TriR& r, int px, int py) {
+    int e0 = __mul24(r.X[2] - r.X[1], py - r.Y[1]) - __mul24(r.Y[2] - r.Y[1], px - r.X[1]);
+    int e1 = __mul24(r.X[0] - r.X[2], py - r.Y[2]) - __mul24(r.Y[0] - r.Y[2], px - r.X[2]);
+    int e2 = __mul24(r.X[1] - r.X[0], py - r.Y[0]) - __mul24(r.Y[1] - r.Y[0], px - r.X[0]);
+    bool ok0 = (e0 > 0) || (e0 == 0 && (r.flags & 2u));
+    bool ok1 = (e1 > 0) || (e1 == 0 && (r.flags & 4u));
+    bool ok2 = (e2 > 0) || (e2 == 0 && (r.flags & 8u));
+    return ok0 && ok1 && ok2;
+}
+
 __device__ __forceinline__ float depth_at(const TriR& r, int px, int py) {
     float z = (r.z0 + r.zx * (float)(px - r.X[0])) + r.zy * (float)(py - r.Y[0]);
     if (!(z > 0.0f)) z = 0.0f;
@@ -183,21 +206,30 @@ __device__ __forceinline__ Foot footprint(float u, float v, int W, int H) {
     f.fx = x - x0f;
     f.fy = y - y0f;
     int x0 = (int)x0f, y0 = (int)y0f;
-    f.xa = ((x0 % W) + W) % W;
-    f.xb = (((x0 + 1) % W) + W) % W;
+    // x0 mod W (non-negative); UVs within a period or two need no division
+    int xa;
+    if (x0 >= 0 && x0 < W) xa = x0;
+    else if (x0 >= W && x0 < 2 * W) xa = x0 - W;
+    else if (x0 < 0 && x0 >= -W) xa = x0 + W;
+    else {
+        xa = x0 % W;
+        if (xa < 0) xa += W;
+    }
+    f.xa = xa;
+    f.xb = (xa + 1 == W) ? 0 : xa + 1;
     f.ya = y0 < 0 ? 0 : (y0 > H - 1 ? H - 1 : y0);
     int y1 = y0 + 1;
     f.yb = y1 < 0 ? 0 : (y1 > H - 1 ? H - 1 : y1);
     return f;
 }
 
-// Bilinear sample of texture t of the perturbed scene (theta + sgn s eps).
+// Bilinear sample of texture t of the perturbed scene (theta + sgn s eps)
+// over a precomputed footprint.
 __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __restrict__ th,
                                            const uint32_t* __restrict__ pb, float e, float sgn, int t,
-                                           float u, float v, float* out) {
-    int W = sc.tex_w[t], H = sc.tex_h[t], C = sc.tex_c[t];
+                                           const Foot& f, float* out) {
+    int W = sc.tex_w[t], C = sc.tex_c[t];
     long long base = sc.tex_off[t];
-    Foot f = footprint(u, v, W, H);
     float w00 = (1.0f - f.fx) * (1.0f - f.fy);
     float w10 = f.fx * (1.0f - f.fy);
     float w01 = (1.0f - f.fx) * f.fy;
@@ -235,12 +267,39 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Face frame of a triangle from its perturbed corners p (original order)
+// and corner UVs: the unit face normal and, for GGX, the tangent frame.
+__device__ __forceinline__ void face_frame(int shading, const float* p, const float* cuv, TriF& F) {
+    float e1v[3], e2v[3], nf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { e1v[c] = p[3 + c] - p[c]; e2v[c] = p[6 + c] - p[c]; }
+    cross3(e1v, e2v, nf);
+    nrm3(nf);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { F.nf[c] = nf[c]; F.T[c] = 0.0f; F.B[c] = 0.0f; }
+    if (shading != 2) return;
+    float du1 = cuv[2] - cuv[0], dv1 = cuv[3] - cuv[1], du2 = cuv[4] - cuv[0], dv2 = cuv[5] - cuv[1];
+    float rr = du1 * dv2 - du2 * dv1;
+    float T[3], B[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[c] = e1v[c] * dv2 - e2v[c] * dv1;
+    if (rr < 0.0f) { T[0] = -T[0]; T[1] = -T[1]; T[2] = -T[2]; }
+    float nt = dot3(nf, T);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[c] = T[c] - nf[c] * nt;
+    nrm3(T);
+    cross3(nf, T, B);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { F.T[c] = T[c]; F.B[c] = B[c]; }
+}
+
 // Colour and UV of pixel (px,py) (subpixel sample coordinates) covered by
 // triangle t: perspective-correct attributes, then unlit / Lambert / GGX.
+// foot0 receives the bilinear footprint of texel class 0 at the pixel.
 __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, const float* __restrict__ th,
                                             const uint32_t* __restrict__ pb, const float* eps, float sgn,
-                                            const TriR& r, const TriS& s, int t, int px, int py,
-                                            float* rgb, float* uvo) {
+                                            const TriR& r, const TriS& s, const TriF& fr, int t, int px, int py,
+                                            float* rgb, float* uvo, Foot& foot0) {
     long long e0, e1, e2;
     (void)inside(r, px, py, e0, e1, e2);
     float fa = (float)r.area2;
@@ -257,16 +316,15 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
     uvo[0] = u;
     uvo[1] = v;
     float alb[3] = {0.0f, 0.0f, 0.0f};
-    if (sc.n_tex > 0) sample_tex(sc, th, pb, eps[1], sgn, 0, u, v, alb);
+    if (sc.n_tex > 0) {
+        foot0 = footprint(u, v, sc.cls_w[0], sc.cls_h[0]);
+        sample_tex(sc, th, pb, eps[1], sgn, 0, foot0, alb);
+    }
     if (sc.shading == 0) {
         rgb[0] = alb[0]; rgb[1] = alb[1]; rgb[2] = alb[2];
         return;
     }
-    float e1v[3], e2v[3], nf[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) { e1v[c] = s.p[3 + c] - s.p[c]; e2v[c] = s.p[6 + c] - s.p[c]; }
-    cross3(e1v, e2v, nf);
-    nrm3(nf);
+    const float* nf = fr.nf;
     if (sc.shading == 1) {
         float ndl = dot3(nf, sc.light);
         if (!(ndl > 0.0f)) ndl = 0.0f;
@@ -276,28 +334,25 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
         return;
     }
     // GGX with a tangent-space normal map in the face's UV frame
-    float du1 = cu1 - cu0, dv1 = cv1 - cv0, du2 = cu2 - cu0, dv2 = cv2 - cv0;
-    float rr = du1 * dv2 - du2 * dv1;
-    float T[3], B[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) T[c] = e1v[c] * dv2 - e2v[c] * dv1;
-    if (rr < 0.0f) { T[0] = -T[0]; T[1] = -T[1]; T[2] = -T[2]; }
-    float nt = dot3(nf, T);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) T[c] = T[c] - nf[c] * nt;
-    nrm3(T);
-    cross3(nf, T, B);
     float nm[3] = {0.5f, 0.5f, 1.0f};
-    if (sc.n_tex > 1) sample_tex(sc, th, pb, eps[2], sgn, 1, u, v, nm);
+    if (sc.n_tex > 1) {
+        int c1 = sc.tex_cls[1];
+        Foot f1 = (c1 == 0) ? foot0 : footprint(u, v, sc.cls_w[c1], sc.cls_h[c1]);
+        sample_tex(sc, th, pb, eps[2], sgn, 1, f1, nm);
+    }
     float tn[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) tn[c] = 2.0f * nm[c] - 1.0f;
     float n[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) n[c] = (T[c] * tn[0] + B[c] * tn[1]) + nf[c] * tn[2];
+    for (int c = 0; c < 3; ++c) n[c] = (fr.T[c] * tn[0] + fr.B[c] * tn[1]) + nf[c] * tn[2];
     nrm3(n);
     float rough = 0.5f;
-    if (sc.n_tex > 2) sample_tex(sc, th, pb, eps[3], sgn, 2, u, v, &rough);
+    if (sc.n_tex > 2) {
+        int c2 = sc.tex_cls[2];
+        Foot f2 = (c2 == 0) ? foot0 : footprint(u, v, sc.cls_w[c2], sc.cls_h[c2]);
+        sample_tex(sc, th, pb, eps[3], sgn, 2, f2, &rough);
+    }
     float P[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

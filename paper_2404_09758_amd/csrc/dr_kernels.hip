@@ -50,8 +50,8 @@ __global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, 
 __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
                                           const uint32_t* __restrict__ pb, float e0, float sgn, int t,
                                           TriR* __restrict__ recR, TriS* __restrict__ recS,
-                                          unsigned* __restrict__ counts, unsigned* __restrict__ bins, int tile_px,
-                                          int cap) {
+                                          TriF* __restrict__ recF, unsigned* __restrict__ counts,
+                                          unsigned* __restrict__ bins, int tile_px, int cap) {
     int vid[3];
     float p[9];
     Vtx v[3];
@@ -104,6 +104,7 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     r.zy = (d2 * fX1 - d1 * fX2) / fa;
     int xmin = min(r.X[0], min(r.X[1], r.X[2])), xmax = max(r.X[0], max(r.X[1], r.X[2]));
     int ymin = min(r.Y[0], min(r.Y[1], r.Y[2])), ymax = max(r.Y[0], max(r.Y[1], r.Y[2]));
+    if (xmax - xmin < 32768 && ymax - ymin < 32768) r.flags |= TRI_SMALL;
     // pixels whose centre 256 x + 128 lies in [min, max]
     int bx0 = max((xmin + 127) >> 8, 0), bx1 = min((xmax - 128) >> 8, vw.W - 1);
     int by0 = max((ymin + 127) >> 8, 0), by1 = min((ymax - 128) >> 8, vw.H - 1);
@@ -117,6 +118,13 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     sh.pad = 0;
     recR[t] = r;
     recS[t] = sh;
+    if (sc.shading != 0) {
+        TriF fr;
+        face_frame(sc.shading, p, sc.cuv + 6 * (long long)t, fr);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) fr.pad[k] = 0;
+        recF[t] = fr;
+    }
     if (bx0 > bx1) return;
     int tx0 = bx0 / tile_px, tx1 = bx1 / tile_px, ty0 = by0 / tile_px, ty1 = by1 / tile_px;
     for (int ty = ty0; ty <= ty1; ++ty)
@@ -137,8 +145,9 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     int pair = item / a.n_views, view = item % a.n_views;
     const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
     setup_tri(sc, a.views.v[view], a.theta, pb, a.pert.eps[0], a.sgn[s], t, a.recR + (long long)slot * sc.n_tris,
-              a.recS + (long long)slot * sc.n_tris, a.counts + (long long)slot * a.max_tiles,
-              a.bins + (long long)slot * a.max_tiles * a.cap, a.tile, a.cap);
+              a.recS + (long long)slot * sc.n_tris, a.recF + (long long)slot * sc.n_tris,
+              a.counts + (long long)slot * a.max_tiles, a.bins + (long long)slot * a.max_tiles * a.cap, a.tile,
+              a.cap);
 }
 
 // ----------------------------------------------------------------- tile --
@@ -168,8 +177,14 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
             int dx = idx - dy * bw;
             int x = x0 + dx, y = y0 + dy;
             int px = 256 * x + 128, py = 256 * y + 128;
-            long long e0, e1, e2;
-            if (inside(r, px, py, e0, e1, e2)) {
+            bool cov;
+            if (r.flags & TRI_SMALL) {
+                cov = inside_small(r, px, py);
+            } else {
+                long long e0, e1, e2;
+                cov = inside(r, px, py, e0, e1, e2);
+            }
+            if (cov) {
                 float z = depth_at(r, px, py);
                 unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | t;
                 atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
@@ -265,6 +280,7 @@ struct TileJob {
     float sgn[2];
     const TriR* recR[2];                 // records of each sign (index = triangle)
     const TriS* recS[2];
+    const TriF* recF[2];
     unsigned* counts[2];                 // bin counters of each sign (index = tile)
     const unsigned* bins[2];             // bin entries of each sign (tile * cap + k)
     int cap;
@@ -362,6 +378,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         unsigned id[NS];
         float rgb[NS][3], uv[NS][2];
         int vids[NS][3];
+        Foot foot[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             unsigned long long k = inpix ? S.key[s][local] : ~0ull;
@@ -369,10 +386,15 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
             uv[s][0] = 0.0f; uv[s][1] = 0.0f;
             vids[s][0] = vids[s][1] = vids[s][2] = -1;
+            foot[s].xa = foot[s].xb = foot[s].ya = foot[s].yb = 0;
+            foot[s].fx = foot[s].fy = 0.0f;
             if (id[s] != DRD_BG) {
                 TriR r = J.recR[s][id[s]];
                 TriS sh = J.recS[s][id[s]];
-                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, (int)id[s], px, py, rgb[s], uv[s]);
+                TriF fr;
+                if (sc.shading != 0) fr = J.recF[s][id[s]];
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id[s], px, py, rgb[s], uv[s],
+                            foot[s]);
                 vids[s][0] = sh.vid[0]; vids[s][1] = sh.vid[1]; vids[s][2] = sh.vid[2];
             }
         }
@@ -434,30 +456,30 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 for (int c = 0; c < sc.n_cls; ++c) {
                     if (!J.act_cls[c]) continue;
                     int W = sc.cls_w[c], H = sc.cls_h[c];
-                    long long base = sc.cls_goff[c];
-                    long long gs[NS][4];
+                    unsigned base = (unsigned)sc.cls_goff[c];
+                    unsigned gs[NS][4];
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
-                        gs[s][0] = gs[s][1] = gs[s][2] = gs[s][3] = -1;
+                        gs[s][0] = gs[s][1] = gs[s][2] = gs[s][3] = HASH_EMPTY;
                         if (id[s] == DRD_BG) continue;
-                        Foot f = footprint(uv[s][0], uv[s][1], W, H);
+                        Foot f = (c == 0) ? foot[s] : footprint(uv[s][0], uv[s][1], W, H);
                         if (sc.tex_mode == 1) {
                             int xn = (f.fx >= 0.5f) ? f.xb : f.xa;
                             int yn = (f.fy >= 0.5f) ? f.yb : f.ya;
-                            gs[s][0] = base + (long long)yn * W + xn;
+                            gs[s][0] = base + (unsigned)(yn * W + xn);
                         } else {
-                            gs[s][0] = base + (long long)f.ya * W + f.xa;
-                            gs[s][1] = base + (long long)f.ya * W + f.xb;
-                            gs[s][2] = base + (long long)f.yb * W + f.xa;
-                            gs[s][3] = base + (long long)f.yb * W + f.xb;
+                            gs[s][0] = base + (unsigned)(f.ya * W + f.xa);
+                            gs[s][1] = base + (unsigned)(f.ya * W + f.xb);
+                            gs[s][2] = base + (unsigned)(f.yb * W + f.xa);
+                            gs[s][3] = base + (unsigned)(f.yb * W + f.xb);
                         }
                     }
 #pragma unroll
                     for (int s = 0; s < NS; ++s)
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            long long g = gs[s][k];
-                            if (g < 0) continue;
+                            unsigned g = gs[s][k];
+                            if (g == HASH_EMPTY) continue;
                             bool dup = false;
 #pragma unroll
                             for (int j2 = 0; j2 < 4; ++j2)
@@ -467,7 +489,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                                 for (int j2 = 0; j2 < 4; ++j2)
                                     if (gs[0][j2] == g) dup = true;
                             }
-                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
+                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, g, q, 1u);
                         }
                 }
             }
@@ -516,6 +538,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
         int slot = li * NS + (s < NS ? s : 0);
         J.recR[s] = a.recR + (long long)slot * sc.n_tris;
         J.recS[s] = a.recS + (long long)slot * sc.n_tris;
+        J.recF[s] = a.recF + (long long)slot * sc.n_tris;
         J.counts[s] = a.counts + (long long)slot * a.max_tiles;
         J.bins[s] = a.bins + (long long)slot * a.max_tiles * a.cap;
     }
@@ -685,8 +708,6 @@ __device__ __forceinline__ int last_le(const char* first, int stride, int n, lon
     return lo;
 }
 
-__global__ void k_batch_begin(unsigned long long* work) { *work = 0ull; }
-
 __global__ void k_batch_end(unsigned* step) { *step = *step + 1u; }
 
 // Signs of every (scene, pair): the blocks of a scene are contiguous and
@@ -724,60 +745,55 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
     int tiles = vw.tiles_x * vw.tiles_y;
     setup_tri(sc, vw, S.theta, S.bits + (long long)I.pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t,
               b.recR + I.rec_off + (long long)s * sc.n_tris, b.recS + I.rec_off + (long long)s * sc.n_tris,
-              b.counts + I.cnt_off + (long long)s * tiles, b.bins + I.bin_off + (long long)s * tiles * I.cap,
-              b.tile, I.cap);
+              b.recF + I.rec_off + (long long)s * sc.n_tris, b.counts + I.cnt_off + (long long)s * tiles,
+              b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap);
 }
 
-// Persistent raster / shade / scatter: workgroups take (item, tile) units
-// from the queue until it is empty.
+// Raster / shade / scatter of every (scene, pair, view, tile) unit in one
+// launch: one workgroup per unit, units in the XCD-aware order of
+// xcd_tile(), items of the costliest scenes first.
 template <int TILE>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile_b(BatchArgs b) {
     __shared__ TileShared<TILE, 0> S;
-    __shared__ unsigned long long next;
-    const float sgn2[2] = {1.0f, -1.0f};
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(b.work, 1ull);
-        __syncthreads();
-        long long w = (long long)next;
-        if (w >= b.total_tiles) break;
-        int it = last_le((const char*)&b.items[0].tile0, sizeof(BItem), b.n_items, w);
-        it = __builtin_amdgcn_readfirstlane(it);
-        const BItem& I = b.items[it];
-        const BScene& Sc = b.scenes[I.scene];
-        const DScene& sc = Sc.sc;
-        const DView& vw = b.views[I.view];
-        int tiles = vw.tiles_x * vw.tiles_y;
-        TileJob J;
-        J.sc = &sc;
-        J.vw = &vw;
-        J.theta = Sc.theta;
-        J.pb = Sc.bits + (long long)I.pair * sc.words;
-        J.eps = Sc.eps;
-        J.sgn[0] = sgn2[0];
-        J.sgn[1] = sgn2[1];
+    long long w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= b.total_tiles) return;
+    int it = last_le((const char*)&b.items[0].tile0, sizeof(BItem), b.n_items, w);
+    it = __builtin_amdgcn_readfirstlane(it);
+    const BItem& I = b.items[it];
+    const BScene& Sc = b.scenes[I.scene];
+    const DScene& sc = Sc.sc;
+    const DView& vw = b.views[I.view];
+    int tiles = vw.tiles_x * vw.tiles_y;
+    TileJob J;
+    J.sc = &sc;
+    J.vw = &vw;
+    J.theta = Sc.theta;
+    J.pb = Sc.bits + (long long)I.pair * sc.words;
+    J.eps = Sc.eps;
+    J.sgn[0] = 1.0f;
+    J.sgn[1] = -1.0f;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            J.recR[s] = b.recR + I.rec_off + (long long)s * sc.n_tris;
-            J.recS[s] = b.recS + I.rec_off + (long long)s * sc.n_tris;
-            J.counts[s] = b.counts + I.cnt_off + (long long)s * tiles;
-            J.bins[s] = b.bins + I.bin_off + (long long)s * tiles * I.cap;
-        }
-        J.cap = I.cap;
-        J.tile = (int)(w - I.tile0);
-        J.stats = b.stats;
-        J.targets = Sc.targets + vw.tgt_off;
-        J.Rp = Sc.R + (long long)I.pair * sc.G;
-        J.K = Sc.K;
-        J.act_pos = Sc.act_pos;
-        J.any_act = Sc.any_act;
-        J.act_cls = Sc.act_cls;
-        J.out_rgb = nullptr;
-        J.out_id = nullptr;
-        J.out_uv = nullptr;
-        J.partial = nullptr;
-        tile_body<TILE, 0>(J, S);
-        __syncthreads();                 // table and keys are reused by the next unit
+    for (int s = 0; s < 2; ++s) {
+        J.recR[s] = b.recR + I.rec_off + (long long)s * sc.n_tris;
+        J.recS[s] = b.recS + I.rec_off + (long long)s * sc.n_tris;
+        J.recF[s] = b.recF + I.rec_off + (long long)s * sc.n_tris;
+        J.counts[s] = b.counts + I.cnt_off + (long long)s * tiles;
+        J.bins[s] = b.bins + I.bin_off + (long long)s * tiles * I.cap;
     }
+    J.cap = I.cap;
+    J.tile = (int)(w - I.tile0);
+    J.stats = b.stats;
+    J.targets = Sc.targets + vw.tgt_off;
+    J.Rp = Sc.R + (long long)I.pair * sc.G;
+    J.K = Sc.K;
+    J.act_pos = Sc.act_pos;
+    J.any_act = Sc.any_act;
+    J.act_cls = Sc.act_cls;
+    J.out_rgb = nullptr;
+    J.out_id = nullptr;
+    J.out_uv = nullptr;
+    J.partial = nullptr;
+    tile_body<TILE, 0>(J, S);
 }
 
 // Fold and step over the groups of every scene: each scene starts on a
@@ -862,11 +878,6 @@ hipError_t launch_step(hipStream_t st, const StepArgs& a) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_begin(hipStream_t st, const BatchArgs& b) {
-    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, st, b.work);
-    return hipGetLastError();
-}
-
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b) {
     hipLaunchKernelGGL(k_signs_b, dim3((unsigned)b.sign_blocks), dim3(256), 0, st, b);
     return hipGetLastError();
@@ -877,11 +888,12 @@ hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, int grid) {
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b) {
     int tb = (b.tile * b.tile > 256) ? 256 : b.tile * b.tile;
-    if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3((unsigned)grid), dim3(tb), 0, st, b);
-    else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3((unsigned)grid), dim3(tb), 0, st, b);
-    else hipLaunchKernelGGL(k_tile_b<32>, dim3((unsigned)grid), dim3(tb), 0, st, b);
+    unsigned grid = (unsigned)b.total_tiles;
+    if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, b);
+    else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, b);
+    else hipLaunchKernelGGL(k_tile_b<32>, dim3(grid), dim3(tb), 0, st, b);
     return hipGetLastError();
 }
 
@@ -898,16 +910,4 @@ hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b) {
 hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b) {
     hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, st, (unsigned*)b.step);
     return hipGetLastError();
-}
-
-// Workgroups of the persistent tile kernel that fit on one CU.
-int batch_tile_blocks_per_cu(int tile) {
-    int n = 0;
-    int tb = (tile * tile > 256) ? 256 : tile * tile;
-    hipError_t e;
-    if (tile == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<8>, tb, 0);
-    else if (tile == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<16>, tb, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_b<32>, tb, 0);
-    if (e != hipSuccess || n < 1) n = 1;
-    return n;
 }

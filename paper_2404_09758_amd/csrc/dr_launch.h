@@ -28,6 +28,7 @@ struct SetupArgs {
     int max_tiles;          // tile slots per (item, sign)
     TriR* recR;
     TriS* recS;
+    TriF* recF;
     unsigned* counts;
     unsigned* bins;
 };
@@ -45,6 +46,7 @@ struct TileArgs {
     int max_tiles;
     const TriR* recR;
     const TriS* recS;
+    const TriF* recF;
     unsigned* counts;
     const unsigned* bins;
     unsigned long long* stats;
@@ -96,11 +98,10 @@ struct StepArgs {
 // ------------------------------------------------------------- batch --
 //
 // A batch runs one optimisation step of many independent scenes with one
-// launch per kernel: every (scene, pair, view) item's tiles are served to a
-// persistent raster/scatter kernel from a work counter.  All descriptors
-// live in device memory and are fixed when the batch is created; the step
-// number is read from a device counter, so the step can be captured once
-// as a graph and replayed.
+// launch per kernel: one raster/scatter launch covers every (scene, pair,
+// view) item's tiles.  All descriptors live in device memory and are fixed
+// when the batch is created; the step number is read from a device counter,
+// so the step can be captured once as a graph and replayed.
 
 struct BScene {
     DScene sc;
@@ -129,7 +130,7 @@ struct BItem {
     long long cnt_off;           // bin counters of sign 0 (sign 1 at + tiles)
     long long bin_off;           // bin entries of sign 0 (sign 1 at + tiles * cap)
     long long setup_blk0;        // first block of this item in the setup launch
-    long long tile0;             // first work unit of this item in the tile queue
+    long long tile0;             // first tile unit of this item in the tile launch
 };
 
 struct BatchArgs {
@@ -142,9 +143,9 @@ struct BatchArgs {
     unsigned long long seed;
     const unsigned* step;        // device step counter (1-based)
     long long sign_blocks, setup_blocks, group_blocks, total_tiles;
-    unsigned long long* work;    // tile queue counter
     TriR* recR;
     TriS* recS;
+    TriF* recF;
     unsigned* counts;
     unsigned* bins;
     unsigned long long* stats;
@@ -165,11 +166,9 @@ hipError_t launch_check_tri(hipStream_t st, const int* tri, long long n, int n_v
 hipError_t launch_fold(hipStream_t st, const FoldArgs& a);
 hipError_t launch_step(hipStream_t st, const StepArgs& a);
 
-hipError_t launch_batch_begin(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b);
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, int grid);
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b);
-int batch_tile_blocks_per_cu(int tile);

@@ -99,3 +99,19 @@ def test_batch_graph_equals_direct_launches():
         assert torch.equal(a.theta[i], b.theta[i])
     st = a.stats()
     assert st["max_bin"] > 0 and st["tile_overflows"] == 0
+
+
+def test_autotuned_shapes_give_identical_results():
+    from paper_2404_09758_amd import autotune
+    sc = make_scenes()[1]
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    th = torch.tensor(sc.flat_params(), device=DEV)
+    tt = torch.tensor(sc.flat_params(True), device=DEV)
+    tg = torch.cat([ctx.render(tt, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views])
+    Q0, K0 = ctx.estimate_grad(th, sc.views, tg, 4, 2, 3, sc.eps)
+    tuning, report = autotune.tune_scene(ctx, th, sc.views, tg, 3, sc.eps, reps=1)
+    assert set(report) == {8, 16, 32}
+    assert ctx.tuning == tuning
+    Q1, K1 = ctx.estimate_grad(th, sc.views, tg, 4, 2, 3, sc.eps)
+    assert torch.equal(Q0, Q1) and torch.equal(K0, K1)
+    assert ctx.stats()["tile_overflows"] == 0 or tuning[1] >= 16

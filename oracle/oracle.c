@@ -723,6 +723,72 @@ int or_estimate(const or_scene* sc, const float* theta, const or_view* views, in
     return 0;
 }
 
+/* Eq. 4 (the full-image estimator of Sec. 3 and 6.1): every parameter of
+ * an active block receives s_i times the quantised difference of the whole
+ * image, q = sum over pixels of q_p (fixed point, so the sum is exact); every
+ * group of an active block counts one contribution per (pair, view). */
+int or_estimate_full(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                     const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                     uint32_t scene_index, const float* eps, const int8_t* signs, int64_t* Q, uint32_t* K,
+                     double* G64, or_stats* st) {
+    int64_t d = or_param_count(sc);
+    int64_t G = or_group_count(sc);
+    int8_t* s = (int8_t*)malloc((size_t)(d > 0 ? d : 1));
+    if (!s) return -1;
+    classes_t cl = texel_classes(sc);
+    for (int32_t n = 0; n < n_pairs; ++n) {
+        if (signs) memcpy(s, signs + (int64_t)n * d, (size_t)d);
+        else or_signs(seed, step, (uint32_t)n, scene_index, d, s);
+        const float* tgt = targets;
+        for (int32_t v = 0; v < n_views; ++v) {
+            const or_view* vw = &views[v];
+            int64_t np = (int64_t)vw->width * vw->height;
+            float* rgb[2];
+            for (int k = 0; k < 2; ++k) {
+                rgb[k] = (float*)malloc(sizeof(float) * 3 * (size_t)np);
+                uint32_t* id = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)np);
+                float* uv = (float*)malloc(sizeof(float) * 2 * (size_t)np);
+                frame_t fr;
+                if (build_frame(&fr, sc, theta, s, k == 0 ? +1 : -1, eps, vw)) return -1;
+                render_frame(sc, vw, &fr, rgb[k], id, uv);
+                free_frame(&fr);
+                free(id);
+                free(uv);
+            }
+            int64_t qsum = 0;
+            double dsum = 0.0;
+            for (int64_t p = 0; p < np; ++p) {
+                float delta = pixel_l2(rgb[0] + 3 * p, tgt + 3 * p) - pixel_l2(rgb[1] + 3 * p, tgt + 3 * p);
+                qsum += or_quantize(delta, st);
+                dsum += (double)delta;
+            }
+            for (int64_t i = 0; i < d; ++i) {
+                float e = eps[block_of(sc, i)];
+                if (e == 0.0f || s[i] == 0) continue;
+                Q[i] += (int64_t)s[i] * qsum;
+                if (G64) G64[i] += (double)s[i] * dsum / (2.0 * (double)e);
+            }
+            for (int64_t g = 0; g < G; ++g) {
+                int active;
+                if (g < sc->n_verts) {
+                    active = eps[0] != 0.0f;
+                } else {
+                    active = 0;
+                    for (int c = 0; c < cl.n; ++c) {
+                        int64_t size = (int64_t)sc->tex_w[cl.first[c]] * sc->tex_h[cl.first[c]];
+                        if (g >= cl.offset[c] && g < cl.offset[c] + size) active = class_active(sc, &cl, eps, c);
+                    }
+                }
+                if (active) K[g] += 1;
+            }
+            for (int k = 0; k < 2; ++k) free(rgb[k]);
+            tgt += 3 * np;
+        }
+    }
+    free(s);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Decode and descent (Sec. 5)                                          */
 /* ------------------------------------------------------------------ */

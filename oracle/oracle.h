@@ -93,6 +93,14 @@ int or_estimate(const or_scene* sc, const float* theta, const or_view* views, in
                 uint32_t scene_index, const float* eps, const int8_t* signs,
                 int64_t* Q, uint32_t* K, double* G64, or_stats* st);
 
+/* Eq. 4, the full-image estimator: like or_estimate, but every parameter
+ * (of a block with eps != 0) receives s_i * sum_p q_p of the whole image and
+ * every such group counts one contribution per (pair, view). */
+int or_estimate_full(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                     const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                     uint32_t scene_index, const float* eps, const int8_t* signs,
+                     int64_t* Q, uint32_t* K, double* G64, or_stats* st);
+
 /* Decode the fixed-point sums into float gradients (averaged). */
 int or_decode(const or_scene* sc, const int64_t* Q, const uint32_t* K, const float* eps,
               int32_t averaging, int32_t n_pairs, float* grad);

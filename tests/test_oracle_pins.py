@@ -600,3 +600,55 @@ def test_T9_tiny_sgd_lowers_loss(oracle_lib):
         o.step(theta, m, v, t, Q, K, sc.eps, 1, kind=S.OPT_SGD, averaging=S.AVG_COUNT, lr=sc.lr)
     l1 = loss(theta)
     assert l1 < 0.92 * l0
+
+
+# ------------------------------------------------ full-image estimator ---
+
+@pytest.mark.parametrize("shading", [S.SHADING_UNLIT, S.SHADING_LAMBERT])
+def test_full_image_onehot_equals_per_pixel_and_eq3(shading, oracle_lib):
+    """With s = e_i the full-image estimator (Eq. 4) and the per-pixel one
+    (Eq. 8) both reduce to the quantised central difference of Eq. 3."""
+    sc = S.make_tiny()
+    sc2 = H.SimpleScene(sc.tri, sc.corner_uv, sc.pos, sc.tex, shading=shading, light_dir=S.unit_light())
+    o = oracle.Oracle(sc2)
+    theta = sc2.flat()
+    tgt, _, _ = o.render(sc2.flat(sc.target_pos, sc.target_tex), sc.views[0])
+    eps = [3e-3, 1e-2]
+    rng = np.random.default_rng(2)
+    _, ids, _ = o.render(theta, sc.views[0])
+    vis_verts = np.unique(sc.tri[np.unique(ids[ids != oracle.BG_ID])].reshape(-1))
+    params = list(3 * rng.choice(vis_verts, 4, replace=False)) + list(3 * sc.n_verts + rng.choice(64 * 64 * 3, 4))
+    for i in params:
+        s = np.zeros((1, o.d), np.int8)
+        s[0, i] = 1
+        Qp, _, _, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, eps, signs_=s)
+        Qf, Kf, _, _ = o.estimate(theta, sc.views, [tgt], 0, 1, 1, eps, signs_=s, full_image=True)
+        fp = o.pixel_loss(theta, sc.views[0], tgt, signs_=s[0], sign=+1, eps=eps)
+        fm = o.pixel_loss(theta, sc.views[0], tgt, signs_=s[0], sign=-1, eps=eps)
+        brute = sum(oracle.quantize(x) for x in (fp - fm).reshape(-1))
+        assert Qf[i] == brute == Qp[i]
+        assert np.count_nonzero(Qf) <= 1
+        assert np.all(Kf == 1)
+
+
+def test_full_image_exhaustive_sign_average_is_gradient(oracle_lib):
+    """Eq. 4 is unbiased for an objective quadratic in the parameters: the
+    mean over all 2^12 sign vectors equals the autograd gradient."""
+    rng = np.random.default_rng(9)
+    tex = rng.random((2, 2, 3)).astype(np.float32)
+    sc = H.quad_scene(tex, extent=1.0)
+    view = H.ndc_view(16, 16)
+    o = oracle.Oracle(sc)
+    theta = sc.flat()
+    tgt = rng.random((16, 16, 3)).astype(np.float32)
+    k, base = 12, 12
+    combos = ((np.arange(2 ** k)[:, None] >> np.arange(k)[None, :]) & 1).astype(np.int8)
+    signs = np.ones((2 ** k, o.d), np.int8)
+    signs[:, base:] = 1 - 2 * combos
+    eps = [0.0, 1e-2]
+    Q, K, G64, _ = o.estimate(theta, [view], [tgt], 0, 1, 2 ** k, eps, signs_=signs, want_g64=True,
+                              full_image=True)
+    _, ids, uv = o.render(theta, view)
+    g_ref = _torch_grad_of_l2(tex, uv, ids != oracle.BG_ID, tgt)
+    assert np.allclose(G64[base:] / 2 ** k, g_ref, rtol=1e-4, atol=1e-5)
+    assert np.all(K[o.G - 4:] == 2 ** k) and np.all(K[:4] == 0)     # texels active, vertices frozen

@@ -169,6 +169,15 @@ dr_status dr_estimate_grad(dr_ctx* ctx, const float* theta, const dr_view* views
                            const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
                            const float* eps, int64_t* Q, uint32_t* K);
 
+/* Eq. 4, the full-image estimator (the baseline Sec. 6.1 compares against):
+ * the same renders, but every parameter of a block with eps > 0 receives
+ *   Q_i += s_i * sum over the image of round(delta_p * 2^32)
+ * per (pair, view), and every group of such a block counts K_g += 1 per
+ * (pair, view).  Arguments as for dr_estimate_grad. */
+dr_status dr_estimate_grad_full(dr_ctx* ctx, const float* theta, const dr_view* views, int32_t n_views,
+                                const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                const float* eps, int64_t* Q, uint32_t* K);
+
 /* Decode Q, K into float gradients: g_i = Q_i 2^-32 / (2 eps_i D_i) with
  * D_i = K of the parameter's group (DR_AVG_COUNT) or n_pairs (DR_AVG_PAIRS,
  * Eq. 9); 0 where eps_i = 0 or D_i = 0.  grad [d] float. */

@@ -186,9 +186,11 @@ class Context:
         K = torch.zeros(self.G, dtype=torch.int32, device=self.device)
         return Q, K
 
-    def estimate_grad(self, theta, views: Sequence, targets, seed, step, n_pairs, eps, Q=None, K=None):
-        """targets: one float32 tensor holding the views' [H,W,3] images
-        concatenated (or a list of them)."""
+    def estimate_grad(self, theta, views: Sequence, targets, seed, step, n_pairs, eps, Q=None, K=None,
+                      full_image=False):
+        """Eq. 8 (per pixel) or, with full_image, Eq. 4, summed over pairs and
+        views into Q, K.  targets: one float32 tensor holding the views'
+        [H,W,3] images concatenated (or a list of them)."""
         dp = _check_tensor(theta, torch.float32, self.device, self.d, "theta")
         if isinstance(targets, (list, tuple)):
             targets = torch.cat([t.reshape(-1) for t in targets])
@@ -199,7 +201,8 @@ class Context:
         dq = _check_tensor(Q, torch.int64, self.device, self.d, "Q")
         dk = _check_tensor(K, torch.int32, self.device, self.G, "K")
         vws = (L.View * len(views))(*[make_view(v) for v in views])
-        self._call("dr_estimate_grad", C.c_void_p(dp), vws, len(views), C.c_void_p(dt), C.c_uint64(seed),
+        self._call("dr_estimate_grad_full" if full_image else "dr_estimate_grad", C.c_void_p(dp), vws, len(views),
+                   C.c_void_p(dt), C.c_uint64(seed),
                    C.c_uint32(step), int(n_pairs), self._eps(eps), C.c_void_p(dq), C.c_void_p(dk))
         return Q, K
 

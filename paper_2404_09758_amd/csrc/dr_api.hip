@@ -107,6 +107,8 @@ struct dr_ctx {
     long long R_pairs = 0;
     uint32_t* bits = nullptr;
     long long bits_pairs = 0;
+    long long* qtot = nullptr;
+    long long qtot_pairs = 0;
     double* partials = nullptr;
     long long partial_slots = 0;
     unsigned long long* stats = nullptr;
@@ -327,7 +329,8 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
 extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->recR, c->recS, c->recF, c->counts, c->bins, c->R, c->bits, c->stats, c->partials};
+    void* ptrs[] = {c->recR, c->recS, c->recF, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
+                    c->qtot};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->timer.destroy();
@@ -464,9 +467,9 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
 
 // ----------------------------------------------------------- estimate --
 
-extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
-                                      const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
-                                      const float* eps, int64_t* Q, uint32_t* K) {
+static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                                 const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                 const float* eps, int64_t* Q, uint32_t* K, bool full) {
     if (!c) return DR_E_INVALID;
     if (!theta || !targets || !Q || !K || !views) return fail(c, DR_E_INVALID, "NULL array argument");
     if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
@@ -494,8 +497,13 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     if (s) return s;
     s = ensure_bits(c, n_pairs);
     if (s) return s;
-    s = grow(c, &c->R, &c->R_pairs, n_pairs, (size_t)c->sc.G * sizeof(long long), true);
-    if (s) return s;
+    if (full) {
+        s = grow(c, &c->qtot, &c->qtot_pairs, n_pairs, sizeof(long long), false);
+        if (s) return s;
+    } else {
+        s = grow(c, &c->R, &c->R_pairs, n_pairs, (size_t)c->sc.G * sizeof(long long), true);
+        if (s) return s;
+    }
 
     DPert dp;
     dp.bits = c->bits;
@@ -542,6 +550,7 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     ta.stats = c->stats;
     ta.targets = targets;
     ta.R = c->R;
+    ta.qtot = c->qtot;
     ta.K = K;
     ta.act_pos = eps[0] != 0.0f;
     ta.any_act = ta.act_pos;
@@ -550,12 +559,14 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
             ta.act_cls[c->sc.tex_cls[t]] = 1;
             ta.any_act = 1;
         }
+    if (full) HIPCHK(c, launch_zero64(c->stream, c->qtot, n_pairs));
     for (long long i0 = 0; i0 < items; i0 += per) {
         int n = (int)std::min(per, items - i0);
         sa.item0 = (int)i0;
         ta.item0 = (int)i0;
         HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
-        HIPCHK(c, c->timer.run(c->stream, K_TILE, [&] { return launch_tile(c->stream, ta, tile, 0, n, max_tiles); }));
+        HIPCHK(c, c->timer.run(c->stream, K_TILE,
+                               [&] { return launch_tile(c->stream, ta, tile, full ? 3 : 0, n, max_tiles); }));
     }
     FoldArgs fa;
     std::memset(&fa, 0, sizeof(fa));
@@ -565,8 +576,24 @@ extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_vi
     fa.n_pairs = n_pairs;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) fa.eps[b] = dp.eps[b];
     fa.Q = (long long*)Q;
-    HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    fa.qtot = c->qtot;
+    fa.K = K;
+    fa.n_views = n_views;
+    if (full) HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_broadcast(c->stream, fa); }));
+    else HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
     return DR_OK;
+}
+
+extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                                      const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                      const float* eps, int64_t* Q, uint32_t* K) {
+    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, false);
+}
+
+extern "C" dr_status dr_estimate_grad_full(dr_ctx* c, const float* theta, const dr_view* views,
+                                           int32_t n_views, const float* targets, uint64_t seed, uint32_t step,
+                                           int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K) {
+    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, true);
 }
 
 // --------------------------------------------------------------- loss --

@@ -298,20 +298,24 @@ struct TileJob {
     float* out_uv;
     // loss
     double* partial;
+    // full-image estimate: the pair's total of fixed-point differences
+    long long* qtot;
 };
 
 // MODE: 0 estimate (both signs, scatter), 1 render (write rgb/id/uv),
-// 2 loss (per-tile sum of the per-pixel L2 error f_{w,h}).
+// 2 loss (per-tile sum of the per-pixel L2 error f_{w,h}), 3 full-image
+// estimate (both signs, per-tile sum of the fixed-point differences).
 template <int TILE, int MODE>
 struct TileShared {
     static constexpr int NPIX = TILE * TILE;
     static constexpr int PPT = NPIX > 256 ? NPIX / 256 : 1;
     static constexpr int TB = NPIX / PPT;
-    static constexpr int NS = MODE == 0 ? 2 : 1;
+    static constexpr int NS = (MODE == 0 || MODE == 3) ? 2 : 1;
     static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
     unsigned long long key[NS][NPIX];
     GroupTable<LOG2T> table;
     double red[MODE == 2 ? TB : 1];
+    long long qred[MODE == 3 ? TB : 1];
 };
 
 template <int TILE, int MODE>
@@ -369,6 +373,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     }
 
     double loss_acc = 0.0;
+    long long qsum = 0;
     for (int j = 0; j < PPT; ++j) {
         int local = tid + j * TB;
         int lx = local % TILE, ly = local / TILE;
@@ -404,6 +409,18 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 const float* tg = J.targets + 3 * pix;
                 float dr = rgb[0][0] - tg[0], dg = rgb[0][1] - tg[1], db = rgb[0][2] - tg[2];
                 loss_acc += (double)((dr * dr + dg * dg) + db * db);
+            }
+        } else if constexpr (MODE == 3) {
+            if (inpix && (id[0] != DRD_BG || id[1] != DRD_BG)) {
+                const float* tg = J.targets + 3 * pix;
+                float t0 = tg[0], t1 = tg[1], t2 = tg[2];
+                float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
+                float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
+                float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
+                float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
+                int flag;
+                qsum += quantize(fp - fm, flag);
+                if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
         } else if constexpr (MODE == 1) {
             if (!inpix) continue;
@@ -505,6 +522,16 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         }
         if (tid == 0) *J.partial = S.red[0];
     }
+    if constexpr (MODE == 3) {
+        // integer sums: the order of the additions does not matter
+        S.qred[tid] = qsum;
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if (tid < w) S.qred[tid] = S.qred[tid] + S.qred[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0 && S.qred[0] != 0) atomicAdd((unsigned long long*)J.qtot, (unsigned long long)S.qred[0]);
+    }
     if constexpr (MODE == 0) {
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
@@ -555,6 +582,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     J.out_id = a.out_id;
     J.out_uv = a.out_uv;
     J.partial = a.partials ? a.partials + (long long)li * a.max_tiles + tile : nullptr;
+    J.qtot = (MODE == 3) ? a.qtot + pair : nullptr;
     tile_body<TILE, MODE>(J, S);
 }
 
@@ -567,6 +595,9 @@ template __global__ void k_tile<32, 1>(TileArgs);
 template __global__ void k_tile<8, 2>(TileArgs);
 template __global__ void k_tile<16, 2>(TileArgs);
 template __global__ void k_tile<32, 2>(TileArgs);
+template __global__ void k_tile<8, 3>(TileArgs);
+template __global__ void k_tile<16, 3>(TileArgs);
+template __global__ void k_tile<32, 3>(TileArgs);
 
 // Per-view loss: the tiles' partial sums added in tile order (one block per
 // view, fixed-order reduction), so the value is reproducible run to run.
@@ -623,6 +654,43 @@ __device__ __forceinline__ void fold_group(const DScene& sc, long long g, long l
         if (acc != 0) Q[i] += acc;
     });
     for (int n = 0; n < n_pairs; ++n) R[(long long)n * sc.G + g] = 0;
+}
+
+// Full-image estimate: every parameter of an active block gets
+// s_i^(n) * T[n] for every pair n; every active group counts one
+// contribution per (pair, view).  T is zeroed by k_zero64 before the call.
+__global__ void __launch_bounds__(256) k_broadcast(FoldArgs a) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const DScene& sc = a.sc;
+    if (g >= sc.G) return;
+    bool active = false;
+    if (g < sc.n_verts) {
+        active = a.eps[0] != 0.0f;
+    } else {
+        for (int c = 0; c < sc.n_cls; ++c) {
+            long long size = (long long)sc.cls_w[c] * sc.cls_h[c];
+            long long texel = g - sc.cls_goff[c];
+            if (texel >= 0 && texel < size)
+                for (int t = 0; t < sc.n_tex; ++t)
+                    if (sc.tex_cls[t] == c && a.eps[1 + t] != 0.0f) active = true;
+        }
+    }
+    if (!active) return;
+    for_params(sc, g, [&](long long i, int b) {
+        if (a.eps[b] == 0.0f) return;
+        long long acc = 0;
+        for (int n = 0; n < a.n_pairs; ++n) {
+            long long r = a.qtot[n];
+            acc += (sign_of(a.bits + (long long)n * sc.words, i) > 0) ? r : -r;
+        }
+        if (acc != 0) a.Q[i] += acc;
+    });
+    a.K[g] += (unsigned)(a.n_pairs * a.n_views);
+}
+
+__global__ void k_zero64(long long* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_fold(FoldArgs a) {
@@ -793,6 +861,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     J.out_id = nullptr;
     J.out_uv = nullptr;
     J.partial = nullptr;
+    J.qtot = nullptr;
     tile_body<TILE, 0>(J, S);
 }
 
@@ -843,7 +912,8 @@ static void launch_tile_t(hipStream_t st, const TileArgs& a, int mode, dim3 grid
     dim3 block((TILE * TILE > 256) ? 256 : TILE * TILE);
     if (mode == 0) hipLaunchKernelGGL((k_tile<TILE, 0>), grid, block, 0, st, a);
     else if (mode == 1) hipLaunchKernelGGL((k_tile<TILE, 1>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_tile<TILE, 2>), grid, block, 0, st, a);
+    else if (mode == 2) hipLaunchKernelGGL((k_tile<TILE, 2>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tile<TILE, 3>), grid, block, 0, st, a);
 }
 
 hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, int n_items, int max_tiles) {
@@ -863,6 +933,17 @@ hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tile
 hipError_t launch_check_tri(hipStream_t st, const int* tri, long long n, int n_verts, unsigned long long* bad) {
     dim3 grid((unsigned)((n + 255) / 256));
     hipLaunchKernelGGL(k_check_tri, grid, dim3(256), 0, st, tri, n, n_verts, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_broadcast(hipStream_t st, const FoldArgs& a) {
+    dim3 grid((unsigned)((a.sc.G + 255) / 256));
+    hipLaunchKernelGGL(k_broadcast, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero64(hipStream_t st, long long* p, int n) {
+    hipLaunchKernelGGL(k_zero64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

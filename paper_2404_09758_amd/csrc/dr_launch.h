@@ -59,6 +59,8 @@ struct TileArgs {
     int any_act;                     // any group is scattered
     // loss mode: per (item, tile) partial sums
     double* partials;
+    // full-image mode: per pair totals of the fixed-point differences
+    long long* qtot;
     // render mode
     float* out_rgb;
     unsigned* out_id;
@@ -72,6 +74,10 @@ struct FoldArgs {
     int n_pairs;
     float eps[1 + DRD_MAX_TEX];
     long long* Q;
+    // full-image estimate
+    const long long* qtot;       // [pairs]
+    unsigned* K;
+    int n_views;
 };
 
 struct OptimConst {
@@ -164,6 +170,8 @@ hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tile
                             int n_views, double* out);
 hipError_t launch_check_tri(hipStream_t st, const int* tri, long long n, int n_verts, unsigned long long* bad);
 hipError_t launch_fold(hipStream_t st, const FoldArgs& a);
+hipError_t launch_broadcast(hipStream_t st, const FoldArgs& a);
+hipError_t launch_zero64(hipStream_t st, long long* p, int n);
 hipError_t launch_step(hipStream_t st, const StepArgs& a);
 
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);

@@ -469,3 +469,43 @@ CONFIGS = {
     "octa": make_octa_small,
     "diff": make_diff_run,
 }
+
+
+def make_soup(n_tris: int, res: int = 512, seed: int = 7, pairs: int = 128) -> Scene:
+    """Triangle soup of the per-pixel vs full-image validation (Sec. 6.1):
+    n_tris independent triangles, each with 12 parameters (its 3 vertices and
+    one RGB colour), unlit, seen from the front.  The colour of triangle t is
+    texel t of a power-of-two colour map whose corner UVs all sit on that
+    texel's centre; nearest-texel mode credits only that texel.  The target
+    is a seeded value-noise image (the paper's target image is not
+    available), so `target_pos`/`target_tex` are unused."""
+    rng = np.random.default_rng(seed * 1000 + n_tris)
+    half = CAM_DIST * math.tan(math.radians(FOVY_DEG) / 2)
+    centres = np.stack([rng.uniform(-half, half, n_tris), rng.uniform(-half, half, n_tris),
+                        rng.uniform(-0.2, 0.2, n_tris)], 1)
+    size = 2.5 * 2 * half / math.sqrt(n_tris)
+    offs = rng.normal(0.0, size / 2, (n_tris, 3, 3))
+    offs[:, :, 2] *= 0.1
+    pos = (centres[:, None, :] + offs).reshape(-1, 3)
+    tri = np.arange(3 * n_tris, dtype=np.int64).reshape(n_tris, 3)
+    a, b, c = pos[tri[:, 0]], pos[tri[:, 1]], pos[tri[:, 2]]
+    flip = np.cross(b - a, c - a)[:, 2] < 0                 # face the camera (+z)
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    w = 1
+    while w * w < n_tris:
+        w *= 2
+    h = w
+    while (h // 2) * w >= n_tris:
+        h //= 2
+    tx, ty = np.arange(n_tris) % w, np.arange(n_tris) // w
+    uv = np.stack([(tx + 0.5) / w, (ty + 0.5) / h], 1).astype(np.float32)
+    corner_uv = np.repeat(uv[:, None, :], 3, axis=1)
+    colours = rng.uniform(0.0, 1.0, (h, w, 3)).astype(np.float32)
+    fy = 1.0 / math.tan(math.radians(FOVY_DEG) / 2)
+    eps_pos = 1.5 * (CAM_DIST / fy) * 2.0 / res
+    sc = Scene(f"soup{n_tris}", tri.astype(np.int32), corner_uv, pos.astype(np.float32), [colours],
+               pos.astype(np.float32), [colours], [look_at_view(res, res, 0.0, 0.0)], shading=SHADING_UNLIT,
+               tex_mode=TEX_NEAREST, eps=[eps_pos, 1.0 / 64.0], lr=[eps_pos, 1.0 / 64.0], n_pairs=pairs,
+               optimizer=OPT_ADAM, seed=seed)
+    sc.target_image = value_noise_2d(res, res, seed * 1000 + 77, channels=3, f0=2).astype(np.float32)
+    return sc

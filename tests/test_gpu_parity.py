@@ -266,3 +266,20 @@ def test_full_size_one_pair_one_view_bit_exact(name):
     rgb_o, id_o, _ = o.render(theta, sc.views[0])
     rgb, ids, _ = ctx.render(dev(theta), sc.views[0])
     assert np.array_equal(host(ids).view(np.uint32), id_o) and np.array_equal(host(rgb), rgb_o)
+
+
+# ------------------------------------------------- full-image estimator --
+
+@pytest.mark.parametrize("name,pairs,tuning", [("tiny", 2, (16, 256, 1)), ("lambert", 3, (8, 4, 0)),
+                                               ("ggx", 2, (32, 256, 0))])
+def test_full_image_estimate_bit_exact(name, pairs, tuning):
+    sc = scene_by_name(name)
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 31, 2, pairs, sc.eps, full_image=True)
+    ctx = api.Context(sc, DEV, tuning=tuning)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 31, 2, pairs, sc.eps, full_image=True)
+    assert np.array_equal(host(K).view(np.uint32), Ko)
+    assert np.array_equal(host(Q), Qo)
+    assert np.count_nonzero(Qo) > 0.9 * o.d

@@ -79,6 +79,7 @@ def lib():
         L.or_estimate.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_uint64, C.c_uint32, C.c_int32,
                                   C.c_uint32, vp, vp, vp, vp, vp, vp]
         L.or_estimate_full.argtypes = L.or_estimate.argtypes
+        L.or_estimate_image.argtypes = L.or_estimate.argtypes
         L.or_decode.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, vp]
         L.or_step.argtypes = [vp, vp, vp, vp, C.c_uint32, vp, vp, vp, C.c_int32, vp, vp]
         _lib = L
@@ -188,8 +189,10 @@ class Oracle:
         return f
 
     def estimate(self, theta, views, targets, seed, step, n_pairs, eps, scene_index=0, signs_=None,
-                 Q=None, K=None, want_g64=False, full_image=False):
-        """Eq. 8 summed over pairs and views (full_image=True: Eq. 4)."""
+                 Q=None, K=None, want_g64=False, full_image=False, image_grad=False):
+        """Eq. 8 summed over pairs and views (full_image=True: Eq. 4).
+        image_grad=True: `targets` are the views' gradients dL/dI of a
+        downstream loss and the per-pixel difference is <g, I+ - I->."""
         th = _c(theta, np.float32)
         vws = (View_ * len(views))(*[make_view(v) for v in views])
         tg = np.concatenate([_c(t, np.float32).reshape(-1) for t in targets])
@@ -201,7 +204,8 @@ class Oracle:
             assert sg.size == n_pairs * self.d
         st = Stats_()
         e = self._eps(eps)
-        fn = lib().or_estimate_full if full_image else lib().or_estimate
+        assert not (full_image and image_grad)
+        fn = lib().or_estimate_full if full_image else (lib().or_estimate_image if image_grad else lib().or_estimate)
         rc = fn(C.byref(self.s), _ptr(th), vws, len(views), _ptr(tg), int(seed), int(step),
                                int(n_pairs), int(scene_index), _ptr(e), _ptr(sg), _ptr(Q), _ptr(K),
                                _ptr(G64), C.byref(st))

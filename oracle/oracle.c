@@ -661,10 +661,22 @@ static int params_of(const or_scene* sc, int64_t g, int64_t* out) {
 /* Estimator: Eq. 8 per pixel, accumulated over pairs and views (Eq. 9) */
 /* ------------------------------------------------------------------ */
 
-int or_estimate(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
-                const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
-                uint32_t scene_index, const float* eps, const int8_t* signs, int64_t* Q, uint32_t* K,
-                double* G64, or_stats* st) {
+/* The per-pixel difference that Eq. 8 scatters.  Loss form: f+ - f- of
+ * the per-pixel L2 error against the target t (Table 1).  Image form: t is
+ * the gradient g of a downstream loss with respect to the pixel's colour
+ * and the difference is <g, I+ - I->, the change of that loss to first
+ * order, so that the estimator approximates the vector-Jacobian product of
+ * the render with g. */
+static float pixel_delta(const float* ip, const float* im, const float* t, int image_form) {
+    if (!image_form) return pixel_l2(ip, t) - pixel_l2(im, t);
+    float d0 = ip[0] - im[0], d1 = ip[1] - im[1], d2 = ip[2] - im[2];
+    return (t[0] * d0 + t[1] * d1) + t[2] * d2;
+}
+
+static int estimate_per_pixel(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                              const float* targets, int image_form, uint64_t seed, uint32_t step,
+                              int32_t n_pairs, uint32_t scene_index, const float* eps, const int8_t* signs,
+                              int64_t* Q, uint32_t* K, double* G64, or_stats* st) {
     int64_t d = or_param_count(sc);
     int8_t* s = (int8_t*)malloc((size_t)(d > 0 ? d : 1));
     if (!s) return -1;
@@ -693,9 +705,7 @@ int or_estimate(const or_scene* sc, const float* theta, const or_view* views, in
             /* G: per pixel, the loss difference goes to the parameters of
              * the groups that contributed to the pixel (Alg. 2). */
             for (int64_t p = 0; p < np; ++p) {
-                float fp = pixel_l2(rgb[0] + 3 * p, tgt + 3 * p);
-                float fm = pixel_l2(rgb[1] + 3 * p, tgt + 3 * p);
-                float delta = fp - fm;
+                float delta = pixel_delta(rgb[0] + 3 * p, rgb[1] + 3 * p, tgt + 3 * p, image_form);
                 gset_t set;
                 set.n = 0;
                 groups_of(sc, eps, id[0][p], uv[0] + 2 * p, &set);
@@ -721,6 +731,22 @@ int or_estimate(const or_scene* sc, const float* theta, const or_view* views, in
     }
     free(s);
     return 0;
+}
+
+int or_estimate(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                uint32_t scene_index, const float* eps, const int8_t* signs, int64_t* Q, uint32_t* K,
+                double* G64, or_stats* st) {
+    return estimate_per_pixel(sc, theta, views, n_views, targets, 0, seed, step, n_pairs, scene_index, eps,
+                              signs, Q, K, G64, st);
+}
+
+int or_estimate_image(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                      const float* grad_image, uint64_t seed, uint32_t step, int32_t n_pairs,
+                      uint32_t scene_index, const float* eps, const int8_t* signs, int64_t* Q, uint32_t* K,
+                      double* G64, or_stats* st) {
+    return estimate_per_pixel(sc, theta, views, n_views, grad_image, 1, seed, step, n_pairs, scene_index, eps,
+                              signs, Q, K, G64, st);
 }
 
 /* Eq. 4 (the full-image estimator of Sec. 3 and 6.1): every parameter of

@@ -93,6 +93,15 @@ int or_estimate(const or_scene* sc, const float* theta, const or_view* views, in
                 uint32_t scene_index, const float* eps, const int8_t* signs,
                 int64_t* Q, uint32_t* K, double* G64, or_stats* st);
 
+/* The image form of or_estimate: grad_image holds, per view, the [H,W,3]
+ * gradient g of a downstream loss with respect to the rendered colours, and
+ * the per-pixel difference is <g_p, I+_p - I-_p> (channels r, g, b in that
+ * order) in place of f+_p - f-_p.  Everything else is as for or_estimate. */
+int or_estimate_image(const or_scene* sc, const float* theta, const or_view* views, int32_t n_views,
+                      const float* grad_image, uint64_t seed, uint32_t step, int32_t n_pairs,
+                      uint32_t scene_index, const float* eps, const int8_t* signs,
+                      int64_t* Q, uint32_t* K, double* G64, or_stats* st);
+
 /* Eq. 4, the full-image estimator: like or_estimate, but every parameter
  * (of a block with eps != 0) receives s_i * sum_p q_p of the whole image and
  * every such group counts one contribution per (pair, view). */

@@ -652,3 +652,138 @@ def test_full_image_exhaustive_sign_average_is_gradient(oracle_lib):
     g_ref = _torch_grad_of_l2(tex, uv, ids != oracle.BG_ID, tgt)
     assert np.allclose(G64[base:] / 2 ** k, g_ref, rtol=1e-4, atol=1e-5)
     assert np.all(K[o.G - 4:] == 2 ** k) and np.all(K[:4] == 0)     # texels active, vertices frozen
+
+
+# ------------------------------------------------ image-gradient form ---
+#
+# The image form scatters <g_p, I+_p - I-_p> for a downstream gradient
+# g = dL/dI in place of f+_p - f-_p, so that Eq. 8 estimates the
+# vector-Jacobian product g^T dI/dtheta of the render.
+
+def _torch_vjp_of_sampling(tex, uv, mask, g):
+    """d/d tex of sum_p <g_p, bilinear(tex, uv_p)> by autograd."""
+    Ht, Wt, _ = tex.shape
+    t = torch.tensor(np.asarray(tex, np.float32), requires_grad=True)
+    tt = t.permute(2, 0, 1)
+    tt = torch.cat([tt[:, :, -1:], tt, tt[:, :, :1]], dim=2)
+    tt = torch.cat([tt[:, :1, :], tt, tt[:, -1:, :]], dim=1)[None]
+    c = _grid_sample_wrap(tt, uv[mask][:, 0].astype(np.float64), uv[mask][:, 1].astype(np.float64), Wt, Ht)
+    (c * torch.as_tensor(g[mask])).sum().backward()
+    return t.grad.numpy().reshape(-1).astype(np.float64)
+
+
+def test_image_form_onehot_texel_recovers_vjp(oracle_lib):
+    """Unlit, bilinear, one texel perturbed by +-delta: the colour is linear
+    in the texel, so <g, I+ - I-> = 2 delta g . dI/dtheta_j and
+    Q_j 2^-32 / (2 delta) is the j-th entry of the vector-Jacobian product."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    _, ids, uv = o.render(theta, sc.views[0])
+    mask = ids != oracle.BG_ID
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((64, 64, 3)).astype(np.float32)
+    g_ref = _torch_vjp_of_sampling(sc.tex[0], uv, mask, g)
+    delta = 1e-2
+    eps = [0.0, delta]
+    base = 3 * sc.n_verts
+    hit = np.nonzero(np.abs(g_ref) > 1e-2)[0]
+    for j in rng.choice(hit, 12, replace=False):
+        s = np.zeros((1, o.d), np.int8)
+        s[0, base + j] = -1 if j % 2 else 1
+        Q, K, G64, _ = o.estimate(theta, sc.views, [g], 0, 1, 1, eps, signs_=s, want_g64=True, image_grad=True)
+        est = Q[base + j] * 2.0 ** -32 / (2 * delta)
+        # I+- carry ~1 ulp(1) of rounding each, times |g| <= ~4 per channel
+        n_pix = int(K[sc.n_verts + j // 3])
+        tol = n_pix * 4e-5
+        assert est == pytest.approx(g_ref[j], rel=1e-4, abs=tol)
+        assert G64[base + j] == pytest.approx(g_ref[j], rel=1e-4, abs=tol)
+        assert np.count_nonzero(Q) == 1
+
+
+@pytest.mark.parametrize("shading", [S.SHADING_UNLIT, S.SHADING_LAMBERT])
+def test_image_form_onehot_equals_linearised_eq3(shading, oracle_lib):
+    """With s = e_i the image form equals the quantised central difference
+    of the linearised loss summed over ALL pixels of two full renders, bit
+    for bit: no pixel outside the contribution set changes colour."""
+    sc = S.make_tiny()
+    sc2 = H.SimpleScene(sc.tri, sc.corner_uv, sc.pos, sc.tex, shading=shading, light_dir=S.unit_light())
+    o = oracle.Oracle(sc2)
+    theta = sc2.flat()
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal((64, 64, 3)).astype(np.float32)
+    eps = [3e-3, 1e-2]
+    _, ids, _ = o.render(theta, sc.views[0])
+    vis_verts = np.unique(sc.tri[np.unique(ids[ids != oracle.BG_ID])].reshape(-1))
+    params = list(3 * rng.choice(vis_verts, 5, replace=False) + rng.integers(0, 3, 5))
+    params += list(3 * sc.n_verts + rng.choice(64 * 64 * 3, 5, replace=False))
+    nonzero = 0
+    for i in params:
+        s = np.zeros((1, o.d), np.int8)
+        s[0, i] = -1 if i % 2 else 1
+        Q, _, _, _ = o.estimate(theta, sc.views, [g], 0, 1, 1, eps, signs_=s, image_grad=True)
+        ip, _, _ = o.render(theta, sc.views[0], signs_=s[0], sign=+1, eps=eps)
+        im, _, _ = o.render(theta, sc.views[0], signs_=s[0], sign=-1, eps=eps)
+        d = ip - im                                   # float32, per channel
+        lin = (g[..., 0] * d[..., 0] + g[..., 1] * d[..., 1]) + g[..., 2] * d[..., 2]
+        brute = sum(oracle.quantize(x) for x in lin.reshape(-1))
+        assert Q[i] == int(s[0, i]) * brute
+        nonzero += brute != 0
+    assert nonzero >= len(params) // 2
+
+
+def test_image_form_exhaustive_sign_average_is_vjp(oracle_lib):
+    """Over all 2^12 sign vectors of a 2x2 RGB texture the mean of the image
+    form equals the vector-Jacobian product exactly (E[s_i s_j] = delta_ij
+    and the unlit bilinear colour is linear in the texels)."""
+    rng = np.random.default_rng(12)
+    tex = rng.random((2, 2, 3)).astype(np.float32)
+    sc = H.quad_scene(tex, extent=1.0)
+    view = H.ndc_view(16, 16)
+    o = oracle.Oracle(sc)
+    theta = sc.flat()
+    g = rng.standard_normal((16, 16, 3)).astype(np.float32)
+    k, base = 12, 12
+    combos = ((np.arange(2 ** k)[:, None] >> np.arange(k)[None, :]) & 1).astype(np.int8)
+    signs = np.ones((2 ** k, o.d), np.int8)
+    signs[:, base:] = 1 - 2 * combos
+    eps = [0.0, 1e-2]
+    Q, K, G64, _ = o.estimate(theta, [view], [g], 0, 1, 2 ** k, eps, signs_=signs, want_g64=True, image_grad=True)
+    _, ids, uv = o.render(theta, view)
+    g_ref = _torch_vjp_of_sampling(tex, uv, ids != oracle.BG_ID, g)
+    assert np.allclose(G64[base:] / 2 ** k, g_ref, rtol=1e-4, atol=1e-5)
+    assert np.allclose(Q[base:] * 2.0 ** -32 / (2 * 1e-2) / 2 ** k, g_ref, rtol=1e-4, atol=1e-5)
+
+
+def test_image_form_equals_loss_form_where_linear(oracle_lib):
+    """For g = dL/dI = 2 (I - T) the image form equals the L2 form wherever
+    the colour is linear in the parameters: f+ - f- = <I+ - I-, I+ + I- - 2T>
+    and I+ + I- = 2 I for a texture-only perturbation of an unlit render."""
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tgt, _, _ = o.render(sc.flat_params(True), sc.views[0])
+    rgb, _, _ = o.render(theta, sc.views[0])
+    g = (2.0 * (rgb.astype(np.float64) - tgt)).astype(np.float32)
+    eps = [0.0, 1e-2]
+    Ql, Kl, Gl, _ = o.estimate(theta, sc.views, [tgt], 7, 2, 4, eps, want_g64=True)
+    Qi, Ki, Gi, _ = o.estimate(theta, sc.views, [g], 7, 2, 4, eps, want_g64=True, image_grad=True)
+    assert np.array_equal(Kl, Ki)
+    base = 3 * sc.n_verts
+    assert np.count_nonzero(Gl[base:]) > 1000
+    # per pixel the two differences agree to fp32 rounding (~2.4e-7 each),
+    # i.e. 1.2e-5 per pixel after / (2 eps); a texel sees <= ~4 pairs x 4 px
+    assert np.abs(Gl - Gi).max() < 64 * 1.2e-5
+    assert np.abs(Gl[base:]).max() > 0.05
+
+
+def test_image_form_antithetic_symmetry_bit_exact(oracle_lib):
+    sc = S.make_tiny()
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    g = np.random.default_rng(1).standard_normal((64, 64, 3)).astype(np.float32)
+    s = oracle.signs(5, 2, 0, 0, o.d)[None]
+    Qa, Ka, _, _ = o.estimate(theta, sc.views, [g], 0, 1, 1, sc.eps, signs_=s, image_grad=True)
+    Qb, Kb, _, _ = o.estimate(theta, sc.views, [g], 0, 1, 1, sc.eps, signs_=-s, image_grad=True)
+    assert np.array_equal(Qa, Qb) and np.array_equal(Ka, Kb)
+    assert np.count_nonzero(Qa) > 100

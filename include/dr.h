@@ -178,6 +178,18 @@ dr_status dr_estimate_grad_full(dr_ctx* ctx, const float* theta, const dr_view* 
                                 const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
                                 const float* eps, int64_t* Q, uint32_t* K);
 
+/* The image form of dr_estimate_grad, for a loss computed downstream of the
+ * render: grad_image (device, the views' [H,W,3] float images concatenated
+ * in view order, like targets) holds dL/dI, and each pixel scatters
+ *   delta_p = <g_p, I+_p - I-_p>   (channels r, g, b summed in that order)
+ * in place of f+_p - f-_p, so that Eq. 8 estimates the vector-Jacobian
+ * product of the render with g; with g = 2 (I - T) it equals the L2 form
+ * wherever the colour is linear in the parameters.  Contribution sets,
+ * Q, K, eps and errors are as for dr_estimate_grad. */
+dr_status dr_estimate_grad_image(dr_ctx* ctx, const float* theta, const dr_view* views, int32_t n_views,
+                                 const float* grad_image, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                 const float* eps, int64_t* Q, uint32_t* K);
+
 /* Decode Q, K into float gradients: g_i = Q_i 2^-32 / (2 eps_i D_i) with
  * D_i = K of the parameter's group (DR_AVG_COUNT) or n_pairs (DR_AVG_PAIRS,
  * Eq. 9); 0 where eps_i = 0 or D_i = 0.  grad [d] float. */

@@ -83,6 +83,8 @@ SIGNATURES = {
                                    C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
     "dr_estimate_grad_full": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
                                         C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
+    "dr_estimate_grad_image": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
+                                         C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
     "dr_decode_grad": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_float), C.c_int32, C.c_int32, _vp]),
     "dr_step": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, _vp, _vp, C.POINTER(C.c_float), C.c_int32,
                           C.POINTER(Optim)]),

@@ -469,7 +469,7 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
 
 static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
                                  const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
-                                 const float* eps, int64_t* Q, uint32_t* K, bool full) {
+                                 const float* eps, int64_t* Q, uint32_t* K, bool full, bool image) {
     if (!c) return DR_E_INVALID;
     if (!theta || !targets || !Q || !K || !views) return fail(c, DR_E_INVALID, "NULL array argument");
     if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
@@ -549,6 +549,7 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     ta.bins = c->bins;
     ta.stats = c->stats;
     ta.targets = targets;
+    ta.img_grad = image ? 1 : 0;
     ta.R = c->R;
     ta.qtot = c->qtot;
     ta.K = K;
@@ -587,13 +588,19 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
 extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
                                       const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
                                       const float* eps, int64_t* Q, uint32_t* K) {
-    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, false);
+    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, false, false);
 }
 
 extern "C" dr_status dr_estimate_grad_full(dr_ctx* c, const float* theta, const dr_view* views,
                                            int32_t n_views, const float* targets, uint64_t seed, uint32_t step,
                                            int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K) {
-    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, true);
+    return estimate_common(c, theta, views, n_views, targets, seed, step, n_pairs, eps, Q, K, true, false);
+}
+
+extern "C" dr_status dr_estimate_grad_image(dr_ctx* c, const float* theta, const dr_view* views,
+                                            int32_t n_views, const float* grad_image, uint64_t seed, uint32_t step,
+                                            int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K) {
+    return estimate_common(c, theta, views, n_views, grad_image, seed, step, n_pairs, eps, Q, K, false, true);
 }
 
 // --------------------------------------------------------------- loss --

@@ -399,3 +399,22 @@ __device__ __forceinline__ long long quantize(float delta, int& flag) {
     }
     return (long long)rintf(delta * 4294967296.0f);
 }
+
+// The per-pixel difference that Eq. 8 scatters, from the colours of the two
+// renders.  Loss form (img == 0): f+ - f- with f the L2 error against the
+// target t (Table 1).  Image form (img != 0): t is the gradient g of a
+// downstream loss with respect to the pixel's colour and the difference is
+// <g, I+ - I->, the first-order change of that loss, so that the estimator
+// approximates the vector-Jacobian product of the render.
+__device__ __forceinline__ float pixel_delta(const float* p, const float* m, const float* t, int img) {
+    float t0 = t[0], t1 = t[1], t2 = t[2];
+    if (img) {
+        float d0 = p[0] - m[0], d1 = p[1] - m[1], d2 = p[2] - m[2];
+        return (t0 * d0 + t1 * d1) + t2 * d2;
+    }
+    float dr0 = p[0] - t0, dg0 = p[1] - t1, db0 = p[2] - t2;
+    float dr1 = m[0] - t0, dg1 = m[1] - t1, db1 = m[2] - t2;
+    float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
+    float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
+    return fp - fm;
+}

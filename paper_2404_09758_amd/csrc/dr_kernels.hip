@@ -287,7 +287,8 @@ struct TileJob {
     int tile;
     unsigned long long* stats;
     // estimate
-    const float* targets;                // this view's target image
+    const float* targets;                // this view's target image (image form: dL/dI)
+    int img;                             // image form of the per-pixel difference
     long long* Rp;                       // group sums of the pair
     unsigned* K;
     int act_pos, any_act;
@@ -412,14 +413,8 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             }
         } else if constexpr (MODE == 3) {
             if (inpix && (id[0] != DRD_BG || id[1] != DRD_BG)) {
-                const float* tg = J.targets + 3 * pix;
-                float t0 = tg[0], t1 = tg[1], t2 = tg[2];
-                float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
-                float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
-                float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
-                float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
                 int flag;
-                qsum += quantize(fp - fm, flag);
+                qsum += quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
                 if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
         } else if constexpr (MODE == 1) {
@@ -439,14 +434,8 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             bool act = inpix && (id[0] != DRD_BG || id[1] != DRD_BG) && J.any_act;
             long long q = 0;
             if (act) {
-                const float* tg = J.targets + 3 * pix;
-                float t0 = tg[0], t1 = tg[1], t2 = tg[2];
-                float dr0 = rgb[0][0] - t0, dg0 = rgb[0][1] - t1, db0 = rgb[0][2] - t2;
-                float dr1 = rgb[1][0] - t0, dg1 = rgb[1][1] - t1, db1 = rgb[1][2] - t2;
-                float fp = (dr0 * dr0 + dg0 * dg0) + db0 * db0;
-                float fm = (dr1 * dr1 + dg1 * dg1) + db1 * db1;
                 int flag;
-                q = quantize(fp - fm, flag);
+                q = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
                 if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
             if (J.act_pos) {
@@ -573,6 +562,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     J.tile = tile;
     J.stats = a.stats;
     J.targets = a.targets ? a.targets + vw.tgt_off : nullptr;
+    J.img = a.img_grad;
     J.Rp = (MODE == 0) ? a.R + (long long)pair * sc.G : nullptr;
     J.K = a.K;
     J.act_pos = a.act_pos;
@@ -852,6 +842,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     J.tile = (int)(w - I.tile0);
     J.stats = b.stats;
     J.targets = Sc.targets + vw.tgt_off;
+    J.img = 0;
     J.Rp = Sc.R + (long long)I.pair * sc.G;
     J.K = Sc.K;
     J.act_pos = Sc.act_pos;

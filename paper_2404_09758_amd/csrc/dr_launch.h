@@ -51,7 +51,8 @@ struct TileArgs {
     const unsigned* bins;
     unsigned long long* stats;
     // estimate mode
-    const float* targets;
+    const float* targets;            // target images, or dL/dI in the image form
+    int img_grad;                    // image form: scatter <dL/dI, I+ - I->
     long long* R;                    // [pairs, G] per-pair group sums
     unsigned* K;                     // [G]
     int act_pos;                     // scatter vertex groups

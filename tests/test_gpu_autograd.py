@@ -104,3 +104,55 @@ def test_diff_run_adam_lowers_loss():
         losses.append(float(loss))
     del lf0
     assert losses[-1] < 0.8 * losses[0]
+
+
+# ------------------------------------------------------ image-output form --
+
+def test_render_forward_and_image_backward_match_oracle():
+    """The images are the oracle's renders bit for bit; the backward of a
+    downstream L1 loss (computed by torch) equals the oracle's image-form
+    estimate for the same dL/dI, averaged over the pairs."""
+    sc = S.make_octa_small()
+    o, tg = _setup(sc)
+    eps = [1e-3, 1e-2]
+    pairs = 16
+    rf = autograd.StochasticRender(sc, pairs, eps=eps, seed=9, device=DEV)
+    pos, alb = _params(sc)
+    imgs = rf(pos, alb)
+    ref = np.stack([o.render(sc.flat_params(), v)[0] for v in sc.views])
+    assert np.array_equal(imgs.detach().cpu().numpy(), ref)
+    target = torch.tensor(np.stack(tg), device=DEV)
+    w = torch.linspace(0.5, 1.5, imgs.shape[2], device=DEV)[None, None, :, None]
+    loss = ((imgs - target).abs() * w).sum()
+    g_img = torch.autograd.grad(loss, imgs, retain_graph=True)[0]
+    loss.backward()
+    Qo, Ko, _, _ = o.estimate(sc.flat_params(), sc.views, list(g_img.cpu().numpy()), 9, 1, pairs, eps,
+                              image_grad=True)
+    go = o.decode(Qo, Ko, eps, S.AVG_PAIRS, pairs)
+    nv = 3 * sc.n_verts
+    assert np.array_equal(pos.grad.cpu().numpy().reshape(-1), go[:nv])
+    assert np.array_equal(alb.grad.cpu().numpy().reshape(-1), go[nv:])
+    assert np.count_nonzero(go) > 0
+
+
+def test_image_form_with_l2_downstream_tracks_loss_form():
+    """With L = ||I - T||^2 computed downstream and frozen positions (the
+    unlit colour is then linear in the albedo) the image form and the L2
+    form give the same gradient up to fp32 rounding of the differences."""
+    sc = S.make_diff()
+    _, tg = _setup(sc)
+    eps = (0.0, 1e-2)
+    pairs = 8
+    target = torch.tensor(np.stack(tg), device=DEV)
+    rf = autograd.StochasticRender(sc, pairs, eps=eps, seed=3, device=DEV)
+    lf = autograd.StochasticRasterLoss(sc, [t for t in target], pairs, eps=eps, seed=3, device=DEV)
+    pos, alb = _params(sc)
+    ((rf(pos, alb) - target) ** 2).sum().backward()
+    ga_img = alb.grad.clone()
+    alb.grad = None
+    lf(pos, alb).backward()
+    ga_l2 = alb.grad
+    assert float(ga_l2.abs().max()) > 0.1
+    # per pixel the two differences differ by ~2 ulp(1) of rounding; a texel
+    # sums ~16 pixels per pair: ~16 * 2.4e-7 / (2 eps) = 2e-4 per pair
+    assert float((ga_img - ga_l2).abs().max()) < 2e-3

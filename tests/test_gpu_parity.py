@@ -283,3 +283,30 @@ def test_full_image_estimate_bit_exact(name, pairs, tuning):
     assert np.array_equal(host(K).view(np.uint32), Ko)
     assert np.array_equal(host(Q), Qo)
     assert np.count_nonzero(Qo) > 0.9 * o.d
+
+
+# --------------------------------------------------- image-gradient form --
+
+@pytest.mark.parametrize("name,pairs,tuning,scale", [("tiny", 2, (16, 256, 1), 1.0), ("lambert", 3, (8, 4, 0), 1.0),
+                                                     ("ggx", 2, (32, 256, 0), 1.0), ("nearest", 1, (16, 256, 1), 1.0),
+                                                     ("octa", 4, (8, 1, 1), 3e5)])
+def test_image_form_estimate_bit_exact(name, pairs, tuning, scale):
+    """dL/dI of an arbitrary downstream loss (seeded normal values, one case
+    scaled so that some differences saturate): Q, K and the counters match
+    the oracle's image form bit for bit."""
+    sc = scene_by_name(name)
+    o = oracle.Oracle(sc)
+    rng = np.random.default_rng(17)
+    g = [(scale * rng.standard_normal((int(v.height), int(v.width), 3))).astype(np.float32) for v in sc.views]
+    theta = sc.flat_params()
+    Qo, Ko, _, st = o.estimate(theta, sc.views, g, 77, 5, pairs, sc.eps, image_grad=True)
+    ctx = api.Context(sc, DEV, tuning=tuning)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(x) for x in g], 77, 5, pairs, sc.eps, image_grad=True)
+    Qg, Kg = host(Q), host(K).view(np.uint32)
+    assert np.array_equal(Kg, Ko)
+    assert np.array_equal(Qg, Qo), f"Q differs at {np.nonzero(Qg != Qo)[0][:10]}"
+    assert np.count_nonzero(Qo) > 0
+    gs = ctx.stats()
+    assert gs["saturations"] == st["saturations"] and gs["nonfinite"] == st["nonfinite"]
+    if scale > 1.0:
+        assert st["saturations"] > 0

@@ -39,7 +39,7 @@ class Scene_(C.Structure):
                 ("tex_c", C.c_int32 * MAX_TEX),
                 ("shading", C.c_int32), ("tex_mode", C.c_int32),
                 ("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3),
-                ("ambient", C.c_float), ("diffuse", C.c_float)]
+                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32)]
 
 
 class View_(C.Structure):
@@ -150,6 +150,8 @@ class Oracle:
             s.light_rgb[i] = float(lc[i])
         s.ambient = float(np.float32(getattr(scene, "ambient", 0.1)))
         s.diffuse = float(np.float32(getattr(scene, "diffuse", 0.9)))
+        s.layers = int(getattr(scene, "layers", 0))
+        self.layers = s.layers
         self.s = s
         self.d = int(lib().or_param_count(C.byref(s)))
         self.G = int(lib().or_group_count(C.byref(s)))
@@ -165,8 +167,9 @@ class Oracle:
         assert th.shape == (self.d,)
         W, H = int(view.width), int(view.height)
         rgb = np.zeros((H, W, 3), np.float32)
-        ids = np.zeros((H, W), np.uint32)
-        uv = np.zeros((H, W, 2), np.float32)
+        deep = (self.layers,) if self.layers > 0 else ()
+        ids = np.zeros((H, W) + deep, np.uint32)
+        uv = np.zeros((H, W) + deep + (2,), np.float32)
         sg = None if signs_ is None else _c(signs_, np.int8)
         e = self._eps(eps if eps is not None else [0.0])
         vw = make_view(view)

@@ -316,6 +316,51 @@ static void rasterize_ids(const or_scene* sc, const tri_setup_t* ts, int W, int 
     free(key);
 }
 
+/* Visibility of semi-transparent geometry (Sec. 4.4 "Transparent
+ * geometry": front-to-back rendering after a sort, with a deep ID buffer):
+ * for every pixel centre, the L covering triangles of least (depth,
+ * triangle index), in increasing order -- the exact per-pixel front-to-back
+ * order, kept by insertion into a sorted list of L packed keys. */
+static void rasterize_deep(const or_scene* sc, const tri_setup_t* ts, int W, int H, int L, uint32_t* id) {
+    int64_t n = (int64_t)W * H * L;
+    uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t p = 0; p < n; ++p) key[p] = ~0ull;
+    for (int32_t t = 0; t < sc->n_tris; ++t) {
+        const tri_setup_t* s = &ts[t];
+        if (!s->ok) continue;
+        int32_t xmin = s->X[0], xmax = s->X[0], ymin = s->Y[0], ymax = s->Y[0];
+        for (int k = 1; k < 3; ++k) {
+            if (s->X[k] < xmin) xmin = s->X[k];
+            if (s->X[k] > xmax) xmax = s->X[k];
+            if (s->Y[k] < ymin) ymin = s->Y[k];
+            if (s->Y[k] > ymax) ymax = s->Y[k];
+        }
+        int x0 = (xmin >> 8) - 1, x1 = (xmax >> 8) + 1, y0 = (ymin >> 8) - 1, y1 = (ymax >> 8) + 1;
+        if (x0 < 0) x0 = 0;
+        if (y0 < 0) y0 = 0;
+        if (x1 > W - 1) x1 = W - 1;
+        if (y1 > H - 1) y1 = H - 1;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                int32_t px = 256 * x + 128, py = 256 * y + 128;
+                int64_t E[3];
+                edges_at(s, px, py, E);
+                if (!covers(s, E)) continue;
+                uint64_t k = ((uint64_t)f2u(depth_at(s, px, py)) << 32) | (uint32_t)t;
+                uint64_t* list = key + ((int64_t)y * W + x) * L;
+                if (k >= list[L - 1]) continue;
+                int j = L - 1;
+                while (j > 0 && list[j - 1] > k) {
+                    list[j] = list[j - 1];
+                    --j;
+                }
+                list[j] = k;
+            }
+    }
+    for (int64_t p = 0; p < n; ++p) id[p] = (key[p] == ~0ull) ? BG_ID : (uint32_t)(key[p] & 0xFFFFFFFFu);
+    free(key);
+}
+
 /* ------------------------------------------------------------------ */
 /* Attributes and shading at a pixel (Sec. 4.4 "Textures")              */
 /* ------------------------------------------------------------------ */
@@ -415,12 +460,18 @@ static void cross3(const float* a, const float* b, float* o) {
  * tangent-space normal map in the face's UV frame.  The colour depends only
  * on the triangle's three vertices and on the texels of its footprint. */
 static void shade(const or_scene* sc, const or_view* vw, const float* th, const tri_setup_t* s,
-                  int32_t t, int32_t px, int32_t py, float* rgb, float* uv_out) {
+                  int32_t t, int32_t px, int32_t py, float* rgb, float* uv_out, float* alpha_out) {
     attr_t a = attributes(sc, s, t, px, py);
     uv_out[0] = a.u;
     uv_out[1] = a.v;
-    float alb[3] = {0.0f, 0.0f, 0.0f};
+    float alb[4] = {0.0f, 0.0f, 0.0f, 1.0f};
     if (sc->n_tex > 0) sample_tex(sc, th, 0, a.u, a.v, alb);
+    /* Reading: the opacity of a semi-transparent surface is the albedo's
+     * fourth channel, clamped to [0, 1]. */
+    float al = alb[3];
+    if (!(al > 0.0f)) al = 0.0f;
+    if (al > 1.0f) al = 1.0f;
+    *alpha_out = al;
     if (sc->shading == 0) {
         rgb[0] = alb[0]; rgb[1] = alb[1]; rgb[2] = alb[2];
         return;
@@ -520,18 +571,37 @@ static void free_frame(frame_t* fr) {
     free(fr->ts);
 }
 
+static int n_layers(const or_scene* sc) { return sc->layers > 0 ? sc->layers : 1; }
+
+/* id [H,W,L], uv [H,W,L,2].  Opaque: the visible triangle's colour.
+ * Semi-transparent (reading): the listed fragments composited front to
+ * back over a black background, C = sum_k T_k alpha_k c_k with T_0 = 1 and
+ * T_{k+1} = T_k (1 - alpha_k), accumulated in list order. */
 static int render_frame(const or_scene* sc, const or_view* vw, frame_t* fr, float* rgb, uint32_t* id,
                         float* uv) {
-    int W = fr->W, H = fr->H;
-    rasterize_ids(sc, fr->ts, W, H, id);
+    int W = fr->W, H = fr->H, L = n_layers(sc);
+    if (sc->layers > 0) rasterize_deep(sc, fr->ts, W, H, L, id);
+    else rasterize_ids(sc, fr->ts, W, H, id);
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             int64_t p = (int64_t)y * W + x;
-            float c[3] = {0.0f, 0.0f, 0.0f}, w[2] = {0.0f, 0.0f};
-            if (id[p] != BG_ID)
-                shade(sc, vw, fr->th, &fr->ts[id[p]], (int32_t)id[p], 256 * x + 128, 256 * y + 128, c, w);
-            rgb[3 * p + 0] = c[0]; rgb[3 * p + 1] = c[1]; rgb[3 * p + 2] = c[2];
-            uv[2 * p + 0] = w[0]; uv[2 * p + 1] = w[1];
+            float out[3] = {0.0f, 0.0f, 0.0f}, T = 1.0f;
+            for (int l = 0; l < L; ++l) {
+                int64_t e = p * L + l;
+                float c[3] = {0.0f, 0.0f, 0.0f}, w[2] = {0.0f, 0.0f}, al = 1.0f;
+                if (id[e] != BG_ID)
+                    shade(sc, vw, fr->th, &fr->ts[id[e]], (int32_t)id[e], 256 * x + 128, 256 * y + 128, c, w,
+                          &al);
+                uv[2 * e + 0] = w[0]; uv[2 * e + 1] = w[1];
+                if (sc->layers == 0) {
+                    out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
+                } else if (id[e] != BG_ID) {
+                    float wt = T * al;
+                    for (int ch = 0; ch < 3; ++ch) out[ch] = out[ch] + wt * c[ch];
+                    T = T * (1.0f - al);
+                }
+            }
+            rgb[3 * p + 0] = out[0]; rgb[3 * p + 1] = out[1]; rgb[3 * p + 2] = out[2];
         }
     return 0;
 }
@@ -539,15 +609,16 @@ static int render_frame(const or_scene* sc, const or_view* vw, frame_t* fr, floa
 int or_render(const or_scene* sc, const float* theta, const int8_t* s, int sign, const float* eps,
               const or_view* view, float* rgb, uint32_t* id, float* uv) {
     int64_t np = (int64_t)view->width * view->height;
+    int64_t ne = np * n_layers(sc);
     frame_t fr;
     if (build_frame(&fr, sc, theta, s, sign, eps, view)) return -1;
     float* c = (float*)malloc(sizeof(float) * 3 * (size_t)np);
-    uint32_t* i = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)np);
-    float* w = (float*)malloc(sizeof(float) * 2 * (size_t)np);
+    uint32_t* i = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)ne);
+    float* w = (float*)malloc(sizeof(float) * 2 * (size_t)ne);
     render_frame(sc, view, &fr, c, i, w);
     if (rgb) memcpy(rgb, c, sizeof(float) * 3 * (size_t)np);
-    if (id) memcpy(id, i, sizeof(uint32_t) * (size_t)np);
-    if (uv) memcpy(uv, w, sizeof(float) * 2 * (size_t)np);
+    if (id) memcpy(id, i, sizeof(uint32_t) * (size_t)ne);
+    if (uv) memcpy(uv, w, sizeof(float) * 2 * (size_t)ne);
     free(c); free(i); free(w);
     free_frame(&fr);
     return 0;
@@ -585,10 +656,11 @@ int64_t or_quantize(float delta, or_stats* st) {
 
 /* ------------------------------------------------------------------ */
 /* Contribution set of a pixel (Sec. 4.4; reading: union over the two   */
-/* perturbed renders, each group once)                                  */
+/* perturbed renders -- and over the layers of a deep ID buffer -- each */
+/* group once)                                                          */
 /* ------------------------------------------------------------------ */
 
-#define MAX_SET 64
+#define MAX_SET 256
 
 typedef struct {
     int n;
@@ -693,10 +765,11 @@ static int estimate_per_pixel(const or_scene* sc, const float* theta, const or_v
             float* rgb[2];
             uint32_t* id[2];
             float* uv[2];
+            int L = n_layers(sc);
             for (int k = 0; k < 2; ++k) {
                 rgb[k] = (float*)malloc(sizeof(float) * 3 * (size_t)np);
-                id[k] = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)np);
-                uv[k] = (float*)malloc(sizeof(float) * 2 * (size_t)np);
+                id[k] = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(np * L));
+                uv[k] = (float*)malloc(sizeof(float) * 2 * (size_t)(np * L));
                 frame_t fr;
                 if (build_frame(&fr, sc, theta, s, k == 0 ? +1 : -1, eps, vw)) return -1;
                 render_frame(sc, vw, &fr, rgb[k], id[k], uv[k]);
@@ -708,8 +781,8 @@ static int estimate_per_pixel(const or_scene* sc, const float* theta, const or_v
                 float delta = pixel_delta(rgb[0] + 3 * p, rgb[1] + 3 * p, tgt + 3 * p, image_form);
                 gset_t set;
                 set.n = 0;
-                groups_of(sc, eps, id[0][p], uv[0] + 2 * p, &set);
-                groups_of(sc, eps, id[1][p], uv[1] + 2 * p, &set);
+                for (int k = 0; k < 2; ++k)
+                    for (int l = 0; l < L; ++l) groups_of(sc, eps, id[k][p * L + l], uv[k] + 2 * (p * L + l), &set);
                 if (set.n == 0) continue;
                 int64_t q = or_quantize(delta, st);
                 for (int gi = 0; gi < set.n; ++gi) {
@@ -772,8 +845,8 @@ int or_estimate_full(const or_scene* sc, const float* theta, const or_view* view
             float* rgb[2];
             for (int k = 0; k < 2; ++k) {
                 rgb[k] = (float*)malloc(sizeof(float) * 3 * (size_t)np);
-                uint32_t* id = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)np);
-                float* uv = (float*)malloc(sizeof(float) * 2 * (size_t)np);
+                uint32_t* id = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(np * n_layers(sc)));
+                float* uv = (float*)malloc(sizeof(float) * 2 * (size_t)(np * n_layers(sc)));
                 frame_t fr;
                 if (build_frame(&fr, sc, theta, s, k == 0 ? +1 : -1, eps, vw)) return -1;
                 render_frame(sc, vw, &fr, rgb[k], id, uv);

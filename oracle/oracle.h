@@ -37,6 +37,10 @@ typedef struct {
     float light_rgb[3];
     float ambient;
     float diffuse;
+    int32_t layers;            /* 0 opaque; 1..8 semi-transparent: the       */
+                               /* nearest `layers` fragments of a pixel are   */
+                               /* composited front to back, alpha = channel 3 */
+                               /* of the albedo (which then has 4 channels)   */
 } or_scene;
 
 typedef struct {
@@ -69,8 +73,9 @@ int64_t or_param_count(const or_scene* sc);
 int64_t or_group_count(const or_scene* sc);
 
 /* Render theta (perturbed by sign*s*eps when s != NULL) from one view.
- * rgb [H,W,3], id [H,W] (0xFFFFFFFF = background), uv [H,W,2]; any output
- * may be NULL.  Returns 0 on success. */
+ * rgb [H,W,3], id [H,W,L] (0xFFFFFFFF = background or an empty layer),
+ * uv [H,W,L,2], with L = max(1, layers); any output may be NULL.  Returns 0
+ * on success. */
 int or_render(const or_scene* sc, const float* theta, const int8_t* s, int sign,
               const float* eps, const or_view* view, float* rgb, uint32_t* id, float* uv);
 

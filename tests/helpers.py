@@ -33,6 +33,7 @@ class SimpleScene:
     light_rgb: np.ndarray = field(default_factory=lambda: np.ones(3, np.float32))
     ambient: float = 0.1
     diffuse: float = 0.9
+    layers: int = 0
 
     @property
     def n_verts(self):
@@ -102,3 +103,28 @@ def sphere_scene(freq, splits=0, res=(96, 80), shading=0, tex_shapes=((48, 48, 3
                    shading=shading, tex_mode=tex_mode, ambient=0.1 if shading == 1 else 0.03,
                    light_rgb=np.full(3, 1.0 if shading != 2 else 3.0, np.float32),
                    eps=list(eps), lr=list(eps), n_pairs=1)
+
+
+def stack_scene(tex, layers, n_quads=3, shading=0):
+    """n_quads axis-aligned quads at NDC depths -0.5, 0, 0.5, ... (front to
+    back), each shifted right and down from the one before so that they
+    overlap partly.  Quad k maps to the k-th of n_quads vertical strips of
+    the RGBA texture, its UVs on texel centres (so its samples never read a
+    neighbouring strip)."""
+    tex = np.asarray(tex, np.float32)
+    Ht, Wt, _ = tex.shape
+    pos, tri, cuv = [], [], []
+    for k in range(n_quads):
+        x0, y0, z = -0.8 + 0.35 * k, 0.8 - 0.35 * k, -0.5 + 0.5 * k
+        e = 0.9
+        base = len(pos)
+        pos += [(x0, y0, z), (x0 + e, y0, z), (x0 + e, y0 - e, z), (x0, y0 - e, z)]
+        u0 = (k * Wt / n_quads + 0.5) / Wt
+        u1 = ((k + 1) * Wt / n_quads - 0.5) / Wt
+        v0, v1 = 0.5 / Ht, (Ht - 0.5) / Ht
+        uvv = [(u0, v0), (u1, v0), (u1, v1), (u0, v1)]
+        for t in ((0, 3, 1), (1, 3, 2)):
+            tri.append(tuple(base + i for i in t))
+            cuv.append([uvv[i] for i in t])
+    return SimpleScene(np.array(tri, np.int32), np.array(cuv, np.float32), np.array(pos, np.float32), [tex],
+                       shading=shading, layers=layers)

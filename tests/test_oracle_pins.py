@@ -787,3 +787,100 @@ def test_image_form_antithetic_symmetry_bit_exact(oracle_lib):
     Qb, Kb, _, _ = o.estimate(theta, sc.views, [g], 0, 1, 1, sc.eps, signs_=-s, image_grad=True)
     assert np.array_equal(Qa, Qb) and np.array_equal(Ka, Kb)
     assert np.count_nonzero(Qa) > 100
+
+
+# ---------------------------------------------- semi-transparent layers ---
+#
+# Sec. 4.4 "Transparent geometry": the L nearest fragments of a pixel in
+# front-to-back order (a deep ID buffer), composited over black, and the
+# estimator's contribution set taken over every listed layer.
+
+def _stack_tex(rng, n_quads=3, per=2):
+    """RGBA texture of n_quads strips, each strip per x 2 texels of random
+    colour; alpha in [0.2, 0.8]."""
+    tex = rng.uniform(0.05, 0.95, (2, n_quads * per, 4)).astype(np.float32)
+    tex[..., 3] = rng.uniform(0.2, 0.8, (2, n_quads * per))
+    return tex
+
+
+@pytest.mark.parametrize("layers", [1, 2, 4])
+def test_deep_ids_are_the_depth_sorted_covering_triangles(layers, oracle_lib):
+    """Layer l of the deep ID buffer is the l-th nearest triangle covering
+    the pixel centre; coverage is taken from opaque renders of each triangle
+    alone (pinned by the raster tests), depth order from the quads' planes."""
+    rng = np.random.default_rng(21)
+    sc = H.stack_scene(_stack_tex(rng), layers)
+    view = H.ndc_view(40, 36)
+    _, ids, _ = oracle.Oracle(sc).render(sc.flat(), view)
+    assert ids.shape == (36, 40, layers)
+    cover = []
+    for t in range(len(sc.tri)):
+        one = H.SimpleScene(sc.tri[t:t + 1], sc.corner_uv[t:t + 1], sc.pos, sc.tex)
+        _, i1, _ = oracle.Oracle(one).render(one.flat(), view)
+        cover.append(i1 != oracle.BG_ID)
+    cover = np.stack(cover, -1)                       # [H, W, F]
+    depth = sc.pos[sc.tri[:, 0], 2]                   # quads are parallel to the screen
+    n_multi = 0
+    for y in range(36):
+        for x in range(40):
+            hit = np.nonzero(cover[y, x])[0]
+            order = hit[np.argsort(depth[hit], kind="stable")][:layers]
+            expect = np.full(layers, oracle.BG_ID, np.uint32)
+            expect[: len(order)] = order
+            assert np.array_equal(ids[y, x], expect), (y, x)
+            n_multi += len(hit) > 1
+    assert n_multi > 100
+
+
+def test_composite_matches_closed_form(oracle_lib):
+    """Strips of uniform colour and opacity: each pixel's colour is
+    sum_k T_k alpha_k c_k with T_{k+1} = T_k (1 - alpha_k), in float64."""
+    rng = np.random.default_rng(22)
+    tex = _stack_tex(rng)
+    for k in range(3):
+        tex[:, 2 * k:2 * k + 2] = tex[0, 2 * k]
+    sc = H.stack_scene(tex, 4)
+    view = H.ndc_view(40, 36)
+    rgb, ids, _ = oracle.Oracle(sc).render(sc.flat(), view)
+    quad_of = np.arange(len(sc.tri)) // 2
+    ref = np.zeros((36, 40, 3))
+    for y in range(36):
+        for x in range(40):
+            T = 1.0
+            for t in ids[y, x]:
+                if t == oracle.BG_ID:
+                    continue
+                c = tex[0, 2 * quad_of[t]].astype(np.float64)
+                ref[y, x] += T * c[3] * c[:3]
+                T *= 1.0 - c[3]
+    assert np.abs(rgb - ref).max() < 2e-6
+    assert (ids[..., 1] != oracle.BG_ID).sum() > 100
+
+
+@pytest.mark.parametrize("shading", [S.SHADING_UNLIT, S.SHADING_LAMBERT])
+def test_layers_onehot_equals_full_image_finite_difference(shading, oracle_lib):
+    """Pin T2 with a deep ID buffer: for s = e_i the per-pixel estimator
+    equals the quantised Eq. 3 over all pixels bit for bit, for vertex
+    coordinates, colour texels and opacity texels of every layer -- so no
+    pixel whose colour depends on theta_i is missing from its set."""
+    rng = np.random.default_rng(23)
+    tex = _stack_tex(rng)
+    sc = H.stack_scene(tex, 2, shading=shading)
+    sc.light_dir = S.unit_light()
+    o = oracle.Oracle(sc)
+    theta = sc.flat()
+    view = H.ndc_view(40, 36)
+    tgt = rng.random((36, 40, 3)).astype(np.float32)
+    eps = [2e-2, 5e-2]
+    params = list(range(3 * sc.n_verts)) + list(3 * sc.n_verts + np.arange(tex.size))
+    nonzero = 0
+    for i in params:
+        s = np.zeros((1, o.d), np.int8)
+        s[0, i] = 1 if i % 3 else -1
+        Q, _, _, _ = o.estimate(theta, [view], [tgt], 0, 1, 1, eps, signs_=s)
+        fp = o.pixel_loss(theta, view, tgt, signs_=s[0], sign=+1, eps=eps)
+        fm = o.pixel_loss(theta, view, tgt, signs_=s[0], sign=-1, eps=eps)
+        brute = sum(oracle.quantize(x) for x in (fp - fm).reshape(-1))
+        assert Q[i] == int(s[0, i]) * brute, i
+        nonzero += brute != 0
+    assert nonzero >= len(params) // 2

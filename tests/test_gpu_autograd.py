@@ -139,7 +139,7 @@ def test_image_form_with_l2_downstream_tracks_loss_form():
     """With L = ||I - T||^2 computed downstream and frozen positions (the
     unlit colour is then linear in the albedo) the image form and the L2
     form give the same gradient up to fp32 rounding of the differences."""
-    sc = S.make_diff()
+    sc = S.CONFIGS["diff"]()
     _, tg = _setup(sc)
     eps = (0.0, 1e-2)
     pairs = 8

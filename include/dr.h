@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 #define DR_MAX_TEX 3
+#define DR_MAX_LAYERS 4
 #define DR_MAX_VIEWS 16
 #define DR_BG_ID 0xFFFFFFFFu
 
@@ -76,6 +77,13 @@ typedef struct {
     float light_dir[3];          /* unit vector towards the light             */
     float light_rgb[3];
     float ambient, diffuse;
+    int32_t layers;              /* 0: opaque.  1..DR_MAX_LAYERS: semi-       */
+                                 /* transparent (Sec. 4.4): the `layers`      */
+                                 /* nearest fragments of each pixel, in depth */
+                                 /* order, composited front to back over      */
+                                 /* black; opacity = the albedo's fourth      */
+                                 /* channel (tex_c[0] must then be 4),        */
+                                 /* clamped to [0, 1].  Needs tile_px <= 16.  */
 } dr_scene;
 
 /* A camera: clip = view_proj * [x y z 1]^T (row-major); pixel (0,0) is the
@@ -140,7 +148,9 @@ int64_t dr_group_count(const dr_ctx* ctx);       /* number of groups G        */
 /* The rasterizer R extended with ID and UV buffers (Sec. 4.4): render theta
  * (perturbed when pert != NULL) from one view.  rgb [H,W,3] float, id [H,W]
  * uint32 (DR_BG_ID where no triangle covers the pixel centre), uv [H,W,2]
- * float (0 on background); any output may be NULL. */
+ * float (0 on background); any output may be NULL.  For a semi-transparent
+ * scene id and uv are deep buffers, [H,W,layers] and [H,W,layers,2], front
+ * to back, unused layers DR_BG_ID and 0. */
 dr_status dr_render(dr_ctx* ctx, const float* theta, const dr_view* view, const dr_perturb* pert,
                     float* rgb, uint32_t* id, float* uv);
 
@@ -246,7 +256,8 @@ typedef struct {
 } dr_batch_scene;
 
 /* Arrays passed in scenes[] must stay valid for the life of the batch.
- * tile_px: 8, 16 or 32 for every scene; first_step >= 1. */
+ * tile_px: 8, 16 or 32 for every scene; first_step >= 1.  Scenes must be
+ * opaque (layers == 0; DR_E_UNSUPPORTED otherwise). */
 dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scenes, int32_t n_scenes, int32_t n_pairs,
                           int32_t tile_px, const dr_optim* opt, uint64_t seed, uint32_t first_step,
                           void* stream);

@@ -25,7 +25,7 @@ class Scene(C.Structure):
                 ("tex_c", C.c_int32 * MAX_TEX),
                 ("shading", C.c_int32), ("tex_mode", C.c_int32),
                 ("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3),
-                ("ambient", C.c_float), ("diffuse", C.c_float)]
+                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32)]
 
 
 class View(C.Structure):

@@ -101,6 +101,8 @@ class Context:
                 s.light_rgb[i] = float(lc[i])
             s.ambient = float(np.float32(scene.ambient))
             s.diffuse = float(np.float32(getattr(scene, "diffuse", 0.9)))
+            s.layers = int(getattr(scene, "layers", 0))
+            self.layers = s.layers
             self._scene = s
             self.n_tex = len(shapes)
             tn = L.Tuning(*tuning)
@@ -141,12 +143,14 @@ class Context:
         return _floats(e, 1 + L.MAX_TEX)
 
     def render(self, theta, view, pert=None, rgb=True, ids=True, uv=True):
-        """pert: None or dict(seed, step, pair, scene_index, sign, eps)."""
+        """pert: None or dict(seed, step, pair, scene_index, sign, eps).
+        Semi-transparent scenes return deep ids [H,W,L] and uv [H,W,L,2]."""
         dp = _check_tensor(theta, torch.float32, self.device, self.d, "theta")
         W, H = int(view.width), int(view.height)
         out_rgb = torch.empty((H, W, 3), dtype=torch.float32, device=self.device) if rgb else None
-        out_id = torch.empty((H, W), dtype=torch.int32, device=self.device) if ids else None
-        out_uv = torch.empty((H, W, 2), dtype=torch.float32, device=self.device) if uv else None
+        deep = (self.layers,) if self.layers > 0 else ()
+        out_id = torch.empty((H, W) + deep, dtype=torch.int32, device=self.device) if ids else None
+        out_uv = torch.empty((H, W) + deep + (2,), dtype=torch.float32, device=self.device) if uv else None
         p = None
         if pert is not None:
             p = L.Perturb()

@@ -216,6 +216,8 @@ static dr_status check_tuning(dr_ctx* c, const dr_tuning* t) {
     if (t->bin_capacity < 1 || t->bin_capacity > (1 << 20))
         return fail(c, DR_E_INVALID, "bin_capacity must be in [1, 2^20]");
     if (t->items_per_launch < 0) return fail(c, DR_E_INVALID, "items_per_launch must be >= 0");
+    if (c->hs.layers > 0 && t->tile_px > 16)
+        return fail(c, DR_E_UNSUPPORTED, "semi-transparent scenes need tile_px 8 or 16");
     return DR_OK;
 }
 
@@ -230,10 +232,12 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     if (s->shading < DR_UNLIT || s->shading > DR_GGX) return DR_E_INVALID;
     if (s->tex_mode != DR_TEX_FOOTPRINT && s->tex_mode != DR_TEX_NEAREST) return DR_E_INVALID;
     if (s->shading != DR_UNLIT && s->n_tex < 1) return DR_E_INVALID;
+    if (s->layers < 0 || s->layers > DR_MAX_LAYERS) return DR_E_INVALID;
+    if (s->layers > 0 && s->n_tex < 1) return DR_E_INVALID;
     long long d = 3ll * s->n_verts;
     for (int t = 0; t < s->n_tex; ++t) {
         if (s->tex_w[t] < 1 || s->tex_h[t] < 1 || s->tex_w[t] > 32768 || s->tex_h[t] > 32768) return DR_E_INVALID;
-        int want = (t == 2) ? 1 : 3;
+        int want = (t == 2) ? 1 : (t == 0 && s->layers > 0 ? 4 : 3);
         if (s->tex_c[t] != want) return DR_E_INVALID;
         d += (long long)s->tex_w[t] * s->tex_h[t] * s->tex_c[t];
     }
@@ -293,6 +297,7 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     }
     sc.shading = s->shading;
     sc.tex_mode = s->tex_mode;
+    sc.layers = s->layers;
     for (int i = 0; i < 3; ++i) {
         sc.light[i] = s->light_dir[i];
         sc.light_rgb[i] = s->light_rgb[i];
@@ -880,6 +885,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
         const dr_batch_scene& s = scenes[i];
         if (!s.ctx || !s.views || !s.targets || !s.theta || !s.Q || !s.K) return DR_E_INVALID;
         if (s.ctx->device != dev) return DR_E_INVALID;
+        if (s.ctx->sc.layers > 0) return DR_E_UNSUPPORTED;     // the batch raster is opaque only
         if (opt->kind == DR_ADAM && (!s.m || !s.v)) return DR_E_INVALID;
         if (s.n_views < 1 || s.n_views > DR_MAX_VIEWS) return DR_E_INVALID;
         if (s.bin_capacity < 0 || s.bin_capacity > (1 << 20)) return DR_E_INVALID;

@@ -14,6 +14,7 @@
 
 #define DRD_BG 0xFFFFFFFFu
 #define DRD_MAX_TEX 3
+#define DRD_MAX_LAYERS 4
 #define DRD_MAX_VIEWS 16
 #define DRD_PI 3.14159265f
 #define DRD_INV_PI 0.318309886f
@@ -31,6 +32,7 @@ struct DScene {
     int cls_w[DRD_MAX_TEX], cls_h[DRD_MAX_TEX];
     long long cls_goff[DRD_MAX_TEX];     // first group of each class
     int shading, tex_mode;
+    int layers;                          // 0 opaque; 1..4 composited fragments
     float light[3], light_rgb[3], ambient, diffuse;
     long long d, G;
     int words;                           // ceil(d / 32) sign words per pair
@@ -224,7 +226,8 @@ __device__ __forceinline__ Foot footprint(float u, float v, int W, int H) {
 }
 
 // Bilinear sample of texture t of the perturbed scene (theta + sgn s eps)
-// over a precomputed footprint.
+// over a precomputed footprint.  out has room for 4 channels; the channel
+// loop is unrolled to 4 so that out stays in registers.
 __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __restrict__ th,
                                            const uint32_t* __restrict__ pb, float e, float sgn, int t,
                                            const Foot& f, float* out) {
@@ -238,12 +241,15 @@ __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __rest
     long long i10 = base + ((long long)f.ya * W + f.xb) * C;
     long long i01 = base + ((long long)f.yb * W + f.xa) * C;
     long long i11 = base + ((long long)f.yb * W + f.xb) * C;
-    for (int c = 0; c < C; ++c) {
-        float t00 = pval(th, i00 + c, e, pb, sgn);
-        float t10 = pval(th, i10 + c, e, pb, sgn);
-        float t01 = pval(th, i01 + c, e, pb, sgn);
-        float t11 = pval(th, i11 + c, e, pb, sgn);
-        out[c] = ((w00 * t00 + w10 * t10) + w01 * t01) + w11 * t11;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c < C) {
+            float t00 = pval(th, i00 + c, e, pb, sgn);
+            float t10 = pval(th, i10 + c, e, pb, sgn);
+            float t01 = pval(th, i01 + c, e, pb, sgn);
+            float t11 = pval(th, i11 + c, e, pb, sgn);
+            out[c] = ((w00 * t00 + w10 * t10) + w01 * t01) + w11 * t11;
+        }
     }
 }
 
@@ -293,13 +299,15 @@ __device__ __forceinline__ void face_frame(int shading, const float* p, const fl
     for (int c = 0; c < 3; ++c) { F.T[c] = T[c]; F.B[c] = B[c]; }
 }
 
-// Colour and UV of pixel (px,py) (subpixel sample coordinates) covered by
-// triangle t: perspective-correct attributes, then unlit / Lambert / GGX.
-// foot0 receives the bilinear footprint of texel class 0 at the pixel.
+// Colour, opacity and UV of pixel (px,py) (subpixel sample coordinates)
+// covered by triangle t: perspective-correct attributes, then unlit /
+// Lambert / GGX.  foot0 receives the bilinear footprint of texel class 0 at
+// the pixel; opacity the albedo's fourth channel clamped to [0, 1] (1 for a
+// three-channel albedo).
 __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, const float* __restrict__ th,
                                             const uint32_t* __restrict__ pb, const float* eps, float sgn,
                                             const TriR& r, const TriS& s, const TriF& fr, int t, int px, int py,
-                                            float* rgb, float* uvo, Foot& foot0) {
+                                            float* rgb, float* uvo, Foot& foot0, float& opacity) {
     long long e0, e1, e2;
     (void)inside(r, px, py, e0, e1, e2);
     float fa = (float)r.area2;
@@ -315,11 +323,15 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
     float v = ((pc0 * cv0 + pc1 * vn1) + pc2 * vn2) / S;
     uvo[0] = u;
     uvo[1] = v;
-    float alb[3] = {0.0f, 0.0f, 0.0f};
+    float alb[4] = {0.0f, 0.0f, 0.0f, 1.0f};
     if (sc.n_tex > 0) {
         foot0 = footprint(u, v, sc.cls_w[0], sc.cls_h[0]);
         sample_tex(sc, th, pb, eps[1], sgn, 0, foot0, alb);
     }
+    float al = alb[3];
+    if (!(al > 0.0f)) al = 0.0f;
+    if (al > 1.0f) al = 1.0f;
+    opacity = al;
     if (sc.shading == 0) {
         rgb[0] = alb[0]; rgb[1] = alb[1]; rgb[2] = alb[2];
         return;
@@ -334,7 +346,7 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
         return;
     }
     // GGX with a tangent-space normal map in the face's UV frame
-    float nm[3] = {0.5f, 0.5f, 1.0f};
+    float nm[4] = {0.5f, 0.5f, 1.0f, 0.0f};
     if (sc.n_tex > 1) {
         int c1 = sc.tex_cls[1];
         Foot f1 = (c1 == 0) ? foot0 : footprint(u, v, sc.cls_w[c1], sc.cls_h[c1]);
@@ -347,11 +359,11 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
 #pragma unroll
     for (int c = 0; c < 3; ++c) n[c] = (fr.T[c] * tn[0] + fr.B[c] * tn[1]) + nf[c] * tn[2];
     nrm3(n);
-    float rough = 0.5f;
+    float rough4[4] = {0.5f, 0.0f, 0.0f, 0.0f};
     if (sc.n_tex > 2) {
         int c2 = sc.tex_cls[2];
         Foot f2 = (c2 == 0) ? foot0 : footprint(u, v, sc.cls_w[c2], sc.cls_h[c2]);
-        sample_tex(sc, th, pb, eps[3], sgn, 2, f2, &rough);
+        sample_tex(sc, th, pb, eps[3], sgn, 2, f2, rough4);
     }
     float P[3];
 #pragma unroll
@@ -369,7 +381,7 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
     if (!(ndv > 0.0f)) ndv = 0.0f;
     if (!(ndh > 0.0f)) ndh = 0.0f;
     if (!(vdh > 0.0f)) vdh = 0.0f;
-    float alpha = rough * rough;
+    float alpha = rough4[0] * rough4[0];
     if (!(alpha > 0.002f)) alpha = 0.002f;
     float a2 = alpha * alpha;
     float dd = (ndh * ndh) * (a2 - 1.0f) + 1.0f;

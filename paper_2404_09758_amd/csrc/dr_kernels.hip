@@ -17,6 +17,8 @@
 // their descriptors as kernel arguments; the batch kernels read them from
 // device memory and cover many scenes per launch.  Both share the bodies
 // below, so they compute the same bits.
+#include <type_traits>
+
 #include "dr_launch.h"
 
 
@@ -161,9 +163,17 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     return x * q + min(x, rem) + k;
 }
 
-template <int TILE>
+// Rasterise triangle t over the tile: one lane per covered pixel.  Opaque
+// (DEEP false): key[pixel] keeps the least depth|id (64-bit atomic min).
+// Deep: key[pixel * DRD_MAX_LAYERS + l] keeps the L least keys in order,
+// by an atomic-min cascade -- the key is offered to layer 0, and whichever
+// of the offered and the resident key is larger moves on to the next layer
+// (an empty slot ends the cascade).  Every layer thus ends with the least
+// key that reached it, i.e. the l-th least key of the pixel, whatever the
+// interleaving of the lanes and waves.
+template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, int py0, int lane,
-                                           unsigned long long* key) {
+                                           unsigned long long* key, int L) {
     int x0 = max((int)r.bx0, px0), x1 = min((int)r.bx1, px0 + TILE - 1);
     int y0 = max((int)r.by0, py0), y1 = min((int)r.by1, py0 + TILE - 1);
     if (x0 > x1 || y0 > y1) return;
@@ -187,7 +197,16 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
             if (cov) {
                 float z = depth_at(r, px, py);
                 unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | t;
-                atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
+                if constexpr (DEEP) {
+                    unsigned long long* list = key + ((y - py0) * TILE + (x - px0)) * DRD_MAX_LAYERS;
+                    for (int l = 0; l < L; ++l) {
+                        unsigned long long old = atomicMin(&list[l], k);
+                        if (old == ~0ull) break;
+                        k = old > k ? old : k;
+                    }
+                } else {
+                    atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
+                }
             }
         }
     }
@@ -352,14 +371,14 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             for (unsigned k = wave; k < cnt[s]; k += NW) {
                 unsigned t = __builtin_amdgcn_readfirstlane(list[k]);
                 TriR r = R[t];
-                raster_tri<TILE>(r, t, px0, py0, lane, S.key[s]);
+                raster_tri<TILE, false>(r, t, px0, py0, lane, S.key[s], 1);
             }
         } else {
             // bin overflow: test every triangle against this tile
             for (int t = wave; t < sc.n_tris; t += NW) {
                 TriR r = R[t];
                 if (!(r.flags & TRI_VALID)) continue;
-                raster_tri<TILE>(r, (unsigned)t, px0, py0, lane, S.key[s]);
+                raster_tri<TILE, false>(r, (unsigned)t, px0, py0, lane, S.key[s], 1);
             }
         }
     }
@@ -399,8 +418,9 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 TriS sh = J.recS[s][id[s]];
                 TriF fr;
                 if (sc.shading != 0) fr = J.recF[s][id[s]];
+                float alpha;
                 shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id[s], px, py, rgb[s], uv[s],
-                            foot[s]);
+                            foot[s], alpha);
                 vids[s][0] = sh.vid[0]; vids[s][1] = sh.vid[1]; vids[s][2] = sh.vid[2];
             }
         }
@@ -530,10 +550,270 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     }
 }
 
+
+// ------------------------------------------------- semi-transparent tile --
+//
+// Sec. 4.4 "Transparent geometry": the raster keeps, per pixel and sign,
+// the L nearest fragments in front-to-back order (a deep ID buffer in LDS,
+// built by the atomic-min cascade of raster_tri), the shading pass
+// composites them over black, C = sum_l T_l alpha_l c_l with
+// T_{l+1} = T_l (1 - alpha_l), and the scatter credits the union over both
+// renders and all listed layers of the layers' vertices and footprint
+// texels, each group once per pixel.  Tiles are 8 or 16 pixels (one pixel
+// per lane).
+
 template <int TILE, int MODE>
+struct DeepShared {
+    static constexpr int NPIX = TILE * TILE;
+    static constexpr int TB = NPIX;
+    static constexpr int NS = (MODE == 0 || MODE == 3) ? 2 : 1;
+    static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
+    unsigned long long key[NS][NPIX * DRD_MAX_LAYERS];
+    GroupTable<LOG2T> table;
+    double red[MODE == 2 ? TB : 1];
+    long long qred[MODE == 3 ? TB : 1];
+};
+
+// Texel groups of one fragment in class c: the bilinear footprint, or the
+// nearest texel (the other entries HASH_EMPTY).
+__device__ __forceinline__ void texel_groups(const DScene& sc, int c, float u, float v, unsigned* gs) {
+    int W = sc.cls_w[c], H = sc.cls_h[c];
+    unsigned base = (unsigned)sc.cls_goff[c];
+    Foot f = footprint(u, v, W, H);
+    if (sc.tex_mode == 1) {
+        int xn = (f.fx >= 0.5f) ? f.xb : f.xa;
+        int yn = (f.fy >= 0.5f) ? f.yb : f.ya;
+        gs[0] = base + (unsigned)(yn * W + xn);
+        gs[1] = gs[2] = gs[3] = HASH_EMPTY;
+    } else {
+        gs[0] = base + (unsigned)(f.ya * W + f.xa);
+        gs[1] = base + (unsigned)(f.ya * W + f.xb);
+        gs[2] = base + (unsigned)(f.yb * W + f.xa);
+        gs[3] = base + (unsigned)(f.yb * W + f.xb);
+    }
+}
+
+template <int TILE, int MODE>
+__device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE, MODE>& S) {
+    using SH = DeepShared<TILE, MODE>;
+    constexpr int NPIX = SH::NPIX, TB = SH::TB, NS = SH::NS;
+    constexpr int NW = TB / 64 > 0 ? TB / 64 : 1;
+    constexpr int LOG2T = SH::LOG2T;
+    constexpr int TSIZE = 1 << LOG2T;
+    constexpr int LM = DRD_MAX_LAYERS;
+    constexpr int NE = NS * LM;                    // fragment entries per pixel
+    const DScene& sc = *J.sc;
+    const DView& vw = *J.vw;
+    const int L = sc.layers;
+    int tx = J.tile % vw.tiles_x, ty = J.tile / vw.tiles_x;
+    int px0 = tx * TILE, py0 = ty * TILE;
+    int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    for (int j = tid; j < NS * NPIX * LM; j += TB) (&S.key[0][0])[j] = ~0ull;
+    if constexpr (MODE == 0) {
+        for (int j = tid; j < TSIZE; j += TB) {
+            S.table.key[j] = HASH_EMPTY;
+            S.table.sum[j] = 0ull;
+            S.table.cnt[j] = 0u;
+        }
+    }
+    __syncthreads();
+
+    unsigned cnt[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        cnt[s] = J.counts[s][J.tile];
+        const TriR* __restrict__ R = J.recR[s];
+        if (cnt[s] <= (unsigned)J.cap) {
+            const unsigned* __restrict__ list = J.bins[s] + (long long)J.tile * J.cap;
+            for (unsigned k = wave; k < cnt[s]; k += NW) {
+                unsigned t = __builtin_amdgcn_readfirstlane(list[k]);
+                TriR r = R[t];
+                raster_tri<TILE, true>(r, t, px0, py0, lane, S.key[s], L);
+            }
+        } else {
+            for (int t = wave; t < sc.n_tris; t += NW) {
+                TriR r = R[t];
+                if (!(r.flags & TRI_VALID)) continue;
+                raster_tri<TILE, true>(r, (unsigned)t, px0, py0, lane, S.key[s], L);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            J.counts[s][J.tile] = 0u;
+            if (cnt[s] > (unsigned)J.cap) atomicAdd(&J.stats[ST_OVERFLOWS], 1ull);
+            atomicMax(&J.stats[ST_MAX_BIN], (unsigned long long)cnt[s]);
+        }
+    }
+
+    int local = tid;
+    int lx = local % TILE, ly = local / TILE;
+    int x = px0 + lx, y = py0 + ly;
+    bool inpix = x < vw.W && y < vw.H;
+    int px = 256 * x + 128, py = 256 * y + 128;
+    long long pix = (long long)y * vw.W + x;
+    unsigned ids[NE];
+    float us[NE], vs[NE];
+    float rgb[NS][3];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
+        float T = 1.0f;
+#pragma unroll
+        for (int l = 0; l < LM; ++l) {
+            int e = s * LM + l;
+            unsigned long long k = (inpix && l < L) ? S.key[s][local * LM + l] : ~0ull;
+            ids[e] = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
+            us[e] = 0.0f;
+            vs[e] = 0.0f;
+            if (ids[e] != DRD_BG) {
+                TriR r = J.recR[s][ids[e]];
+                TriS sh = J.recS[s][ids[e]];
+                TriF fr;
+                if (sc.shading != 0) fr = J.recF[s][ids[e]];
+                float c[3], uv[2], al;
+                Foot f0;
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)ids[e], px, py, c, uv, f0, al);
+                float wt = T * al;
+                rgb[s][0] = rgb[s][0] + wt * c[0];
+                rgb[s][1] = rgb[s][1] + wt * c[1];
+                rgb[s][2] = rgb[s][2] + wt * c[2];
+                T = T * (1.0f - al);
+                us[e] = uv[0];
+                vs[e] = uv[1];
+            }
+        }
+    }
+
+    if constexpr (MODE == 1) {
+        if (inpix) {
+            if (J.out_rgb) {
+                J.out_rgb[3 * pix + 0] = rgb[0][0];
+                J.out_rgb[3 * pix + 1] = rgb[0][1];
+                J.out_rgb[3 * pix + 2] = rgb[0][2];
+            }
+#pragma unroll
+            for (int l = 0; l < LM; ++l) {
+                if (l >= L) break;
+                long long e = pix * L + l;
+                if (J.out_id) J.out_id[e] = ids[l];
+                if (J.out_uv) {
+                    J.out_uv[2 * e + 0] = us[l];
+                    J.out_uv[2 * e + 1] = vs[l];
+                }
+            }
+        }
+        return;
+    }
+    if constexpr (MODE == 2) {
+        double loss_acc = 0.0;
+        if (inpix) {
+            const float* tg = J.targets + 3 * pix;
+            float dr = rgb[0][0] - tg[0], dg = rgb[0][1] - tg[1], db = rgb[0][2] - tg[2];
+            loss_acc = (double)((dr * dr + dg * dg) + db * db);
+        }
+        S.red[tid] = loss_acc;
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if (tid < w) S.red[tid] = S.red[tid] + S.red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) *J.partial = S.red[0];
+        return;
+    }
+    // lists fill from the front: an empty first layer means an empty list
+    bool any = ids[0] != DRD_BG;
+    if constexpr (NS == 2) any = any || ids[LM] != DRD_BG;
+    if constexpr (MODE == 3) {
+        long long qsum = 0;
+        if (inpix && any) {
+            int flag;
+            qsum = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
+            if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
+        }
+        S.qred[tid] = qsum;
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if (tid < w) S.qred[tid] = S.qred[tid] + S.qred[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0 && S.qred[0] != 0) atomicAdd((unsigned long long*)J.qtot, (unsigned long long)S.qred[0]);
+        return;
+    }
+    if constexpr (MODE == 0) {
+        bool act = inpix && any && J.any_act;
+        if (act) {
+            int flag;
+            long long q = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
+            if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
+            if (J.act_pos) {
+                int vid[NE][3];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    vid[e][0] = vid[e][1] = vid[e][2] = -1;
+                    if (ids[e] != DRD_BG) {
+                        TriS sh = J.recS[e / LM][ids[e]];
+                        vid[e][0] = sh.vid[0]; vid[e][1] = sh.vid[1]; vid[e][2] = sh.vid[2];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    if (ids[e] == DRD_BG) continue;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        int g = vid[e][k];
+                        bool dup = false;
+#pragma unroll
+                        for (int e2 = 0; e2 < e; ++e2)
+                            dup = dup || g == vid[e2][0] || g == vid[e2][1] || g == vid[e2][2];
+                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
+                    }
+                }
+            }
+            for (int c = 0; c < sc.n_cls; ++c) {
+                if (!J.act_cls[c]) continue;
+                unsigned gs[NE][4];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    gs[e][0] = gs[e][1] = gs[e][2] = gs[e][3] = HASH_EMPTY;
+                    if (ids[e] != DRD_BG) texel_groups(sc, c, us[e], vs[e], gs[e]);
+                }
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        unsigned g = gs[e][k];
+                        if (g == HASH_EMPTY) continue;
+                        bool dup = false;
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2)
+                            if (k2 < k && gs[e][k2] == g) dup = true;
+#pragma unroll
+                        for (int e2 = 0; e2 < e; ++e2)
+                            dup = dup || g == gs[e2][0] || g == gs[e2][1] || g == gs[e2][2] || g == gs[e2][3];
+                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, g, q, 1u);
+                    }
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < TSIZE; j += TB) {
+            unsigned g = S.table.key[j];
+            if (g != HASH_EMPTY) global_add(J.Rp, J.K, (long long)g, (long long)S.table.sum[j], S.table.cnt[j]);
+        }
+    }
+}
+
+// One (item, tile) of a single-scene launch: opaque or semi-transparent
+// body.  The job is built here, in the kernel itself, so that the argument
+// block is read in place from the kernel-argument segment.
+template <int TILE, int MODE, bool DEEP>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_tile(TileArgs a) {
-    __shared__ TileShared<TILE, MODE> S;
-    constexpr int NS = TileShared<TILE, MODE>::NS;
+    using SH = std::conditional_t<DEEP, DeepShared<TILE, MODE>, TileShared<TILE, MODE>>;
+    __shared__ SH S;
+    constexpr int NS = SH::NS;
     const DScene& sc = a.sc;
     int li = blockIdx.y;
     int item = a.item0 + li;
@@ -573,21 +853,9 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     J.out_uv = a.out_uv;
     J.partial = a.partials ? a.partials + (long long)li * a.max_tiles + tile : nullptr;
     J.qtot = (MODE == 3) ? a.qtot + pair : nullptr;
-    tile_body<TILE, MODE>(J, S);
+    if constexpr (DEEP) tile_body_deep<TILE, MODE>(J, S);
+    else tile_body<TILE, MODE>(J, S);
 }
-
-template __global__ void k_tile<8, 0>(TileArgs);
-template __global__ void k_tile<16, 0>(TileArgs);
-template __global__ void k_tile<32, 0>(TileArgs);
-template __global__ void k_tile<8, 1>(TileArgs);
-template __global__ void k_tile<16, 1>(TileArgs);
-template __global__ void k_tile<32, 1>(TileArgs);
-template __global__ void k_tile<8, 2>(TileArgs);
-template __global__ void k_tile<16, 2>(TileArgs);
-template __global__ void k_tile<32, 2>(TileArgs);
-template __global__ void k_tile<8, 3>(TileArgs);
-template __global__ void k_tile<16, 3>(TileArgs);
-template __global__ void k_tile<32, 3>(TileArgs);
 
 // Per-view loss: the tiles' partial sums added in tile order (one block per
 // view, fixed-order reduction), so the value is reproducible run to run.
@@ -901,14 +1169,29 @@ hipError_t launch_setup(hipStream_t st, const SetupArgs& a, int n_items) {
 template <int TILE>
 static void launch_tile_t(hipStream_t st, const TileArgs& a, int mode, dim3 grid) {
     dim3 block((TILE * TILE > 256) ? 256 : TILE * TILE);
-    if (mode == 0) hipLaunchKernelGGL((k_tile<TILE, 0>), grid, block, 0, st, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_tile<TILE, 1>), grid, block, 0, st, a);
-    else if (mode == 2) hipLaunchKernelGGL((k_tile<TILE, 2>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_tile<TILE, 3>), grid, block, 0, st, a);
+    if (mode == 0) hipLaunchKernelGGL((k_tile<TILE, 0, false>), grid, block, 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_tile<TILE, 1, false>), grid, block, 0, st, a);
+    else if (mode == 2) hipLaunchKernelGGL((k_tile<TILE, 2, false>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tile<TILE, 3, false>), grid, block, 0, st, a);
+}
+
+template <int TILE>
+static void launch_tile_deep_t(hipStream_t st, const TileArgs& a, int mode, dim3 grid) {
+    dim3 block(TILE * TILE);
+    if (mode == 0) hipLaunchKernelGGL((k_tile<TILE, 0, true>), grid, block, 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_tile<TILE, 1, true>), grid, block, 0, st, a);
+    else if (mode == 2) hipLaunchKernelGGL((k_tile<TILE, 2, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tile<TILE, 3, true>), grid, block, 0, st, a);
 }
 
 hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, int n_items, int max_tiles) {
     dim3 grid((unsigned)max_tiles, (unsigned)n_items);
+    if (a.sc.layers > 0) {
+        if (tile == 8) launch_tile_deep_t<8>(st, a, mode, grid);
+        else if (tile == 16) launch_tile_deep_t<16>(st, a, mode, grid);
+        else return hipErrorInvalidValue;           // deep buffers fit LDS for tiles <= 16
+        return hipGetLastError();
+    }
     if (tile == 8) launch_tile_t<8>(st, a, mode, grid);
     else if (tile == 16) launch_tile_t<16>(st, a, mode, grid);
     else launch_tile_t<32>(st, a, mode, grid);

@@ -293,6 +293,7 @@ class Scene:
     averaging: int = AVG_COUNT
     steps: int = 1
     seed: int = 0
+    layers: int = 0                 # 0 opaque; 1..4 semi-transparent (albedo RGBA)
 
     @property
     def n_verts(self):

@@ -310,3 +310,98 @@ def test_image_form_estimate_bit_exact(name, pairs, tuning, scale):
     assert gs["saturations"] == st["saturations"] and gs["nonfinite"] == st["nonfinite"]
     if scale > 1.0:
         assert st["saturations"] > 0
+
+
+# ----------------------------------------------- semi-transparent layers --
+
+def layered_scene(name):
+    """Semi-transparent scenes: a sphere with an RGBA albedo (front and back
+    faces both seen) over several tiles, and three overlapping quads."""
+    if name == "sphere2":
+        sc = H.sphere_scene(6, 0, res=(96, 80), shading=S.SHADING_UNLIT, tex_shapes=((48, 48, 4),), seed=5,
+                            views=2)
+        sc.layers = 2
+        return sc
+    if name == "sphere4_lambert":
+        sc = H.sphere_scene(5, 0, res=(72, 88), shading=S.SHADING_LAMBERT, tex_shapes=((32, 32, 4),), seed=6,
+                            views=1)
+        sc.layers = 4
+        return sc
+    if name == "stack3":
+        rng = np.random.default_rng(8)
+        tex = rng.uniform(0.05, 0.95, (2, 6, 4)).astype(np.float32)
+        sc = H.stack_scene(tex, 3)
+        sc.views = [H.ndc_view(40, 36)]
+        sc.target_pos = sc.pos
+        sc.target_tex = [rng.uniform(0.05, 0.95, (2, 6, 4)).astype(np.float32)]
+        sc.eps = [2e-2, 5e-2]
+        sc.flat_params = lambda target=False: sc.flat(sc.target_pos if target else sc.pos,
+                                                      sc.target_tex if target else sc.tex)
+        return sc
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["sphere2", "sphere4_lambert", "stack3"])
+@pytest.mark.parametrize("tile,cap", [(8, 256), (16, 256), (16, 1)])
+def test_layered_render_bit_exact(name, tile, cap):
+    sc = layered_scene(name)
+    o = oracle.Oracle(sc)
+    ctx = api.Context(sc, DEV, tuning=(tile, cap, 1))
+    theta = sc.flat_params()
+    for v in sc.views:
+        rgb_o, id_o, uv_o = o.render(theta, v)
+        rgb, ids, uv = ctx.render(dev(theta), v)
+        assert np.array_equal(host(ids).view(np.uint32), id_o)
+        assert np.array_equal(host(uv), uv_o)
+        assert np.array_equal(host(rgb), rgb_o)
+        assert (id_o[..., 1] != oracle.BG_ID).sum() > 20          # some pixels see two layers
+
+
+@pytest.mark.parametrize("name,pairs,tuning,form", [("sphere2", 2, (16, 256, 0), "loss"),
+                                                    ("sphere4_lambert", 2, (8, 4, 1), "loss"),
+                                                    ("stack3", 3, (16, 256, 1), "loss"),
+                                                    ("sphere2", 2, (8, 256, 0), "image"),
+                                                    ("stack3", 2, (16, 1, 0), "full")])
+def test_layered_estimate_bit_exact(name, pairs, tuning, form):
+    sc = layered_scene(name)
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    if form == "image":
+        rng = np.random.default_rng(3)
+        tg = [rng.standard_normal((int(v.height), int(v.width), 3)).astype(np.float32) for v in sc.views]
+    else:
+        tg = targets_of(o, sc)
+    kw = {"image_grad": form == "image", "full_image": form == "full"}
+    Qo, Ko, _, st = o.estimate(theta, sc.views, tg, 5, 9, pairs, sc.eps, **kw)
+    ctx = api.Context(sc, DEV, tuning=tuning)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 5, 9, pairs, sc.eps, **kw)
+    Qg, Kg = host(Q), host(K).view(np.uint32)
+    assert np.array_equal(Kg, Ko), f"K differs at {np.nonzero(Kg != Ko)[0][:10]}"
+    assert np.array_equal(Qg, Qo), f"Q differs at {np.nonzero(Qg != Qo)[0][:10]}"
+    assert np.count_nonzero(Qo) > 0
+    gs = ctx.stats()
+    assert gs["saturations"] == st["saturations"] and gs["nonfinite"] == st["nonfinite"]
+
+
+def test_layered_loss_matches_oracle():
+    sc = layered_scene("sphere2")
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    loss = host(ctx.loss(dev(theta), sc.views, [dev(t) for t in tg]))
+    ref = [o.pixel_loss(theta, v, t).astype(np.float64).sum() for v, t in zip(sc.views, tg)]
+    assert np.allclose(loss, ref, rtol=1e-12)
+
+
+def test_layered_scene_argument_checks():
+    sc = layered_scene("sphere2")
+    with pytest.raises(api.DRError):
+        api.Context(sc, DEV, tuning=(32, 256, 0))          # deep buffers need tiles <= 16
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    with pytest.raises(api.DRError):
+        ctx.set_tuning(32, 256, 0)
+    bad = H.sphere_scene(4, 0, res=(32, 32), tex_shapes=((16, 16, 3),), seed=1)
+    bad.layers = 2                                          # opacity needs an RGBA albedo
+    with pytest.raises(api.DRError):
+        api.Context(bad, DEV)

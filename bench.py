@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny", "batch64", "soup"])
+    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny", "batch64", "soup", "layers"])
     ap.add_argument("--soup-steps", type=int, default=100, help="Adam steps per run of the soup config")
     ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
     ap.add_argument("--no-cpu", action="store_true")
@@ -209,6 +209,8 @@ def main():
         return main_batch64(args, torch, api, autotune, batch, scenes, dev)
     if args.config == "soup":
         return main_soup(args, torch, api, scenes, dev)
+    if args.config == "layers":
+        return main_layers(args, torch, api, autotune, scenes, dev)
     sc = scenes.CONFIGS[args.config]()
     ctx = api.Context(sc, dev, tuning=(16, 256, 0))
     th0 = torch.tensor(sc.flat_params(), device=dev)
@@ -356,6 +358,50 @@ def main_soup(args, torch, api, scenes, dev):
            "config": {"workload": "soup: 1K/10K/100K-triangle soups, 12 params per triangle, unlit, "
                                   "value-noise target"},
            "data": "synthetic", "n_gpus": 1, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def main_layers(args, torch, api, autotune, scenes, dev):
+    """Semi-transparent geometry: the same 20480-triangle, 512^2, 4-view x
+    8-pair step with 0 (opaque), 2 and 4 composited layers per pixel; per
+    layer count the step rate, the raster/scatter kernel's time and its
+    algorithmic bandwidth, and the oracle on one (pair, view) item."""
+    rows = []
+    for layers in (0, 2, 4):
+        sc = scenes.make_layered(layers)
+        ctx = api.Context(sc, dev, tuning=(16, 256, 0))
+        th0 = torch.tensor(sc.flat_params(), device=dev)
+        tt = torch.tensor(sc.flat_params(True), device=dev)
+        tg = torch.cat([ctx.render(tt, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views])
+        tiles = (8, 16) if layers > 0 else (8, 16, 32)
+        (tile, cap, _), _ = autotune.tune_scene(ctx, th0, sc.views, tg, sc.n_pairs, sc.eps, tiles=tiles)
+        th = th0.clone()
+        m = torch.zeros_like(th)
+        v = torch.zeros_like(th)
+        r = run_mode(ctx, sc, th, m, v, tg, sc.eps, args.steps, args.warmup, (tile, cap, 0), api, torch)
+        tm = r["timing"]
+        px = sc.n_pairs * sum(vw.width * vw.height for vw in sc.views)
+        tile_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
+        alg = BYTES_PER_PIXEL_ESTIMATE * px / (tm["tile_launches"] / args.steps)
+        row = {"layers": layers, "steps_per_s": 1e3 / r["ms_per_step"], "ms_per_step": r["ms_per_step"],
+               "tile_px": tile, "bin_capacity": cap, "pixel_estimates_per_s": px * 1e3 / r["ms_per_step"],
+               "contributions_per_step": r["contributions_per_step"],
+               "roofline": {"bound": "hbm", "achieved": alg / (tile_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": alg / (tile_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": f"k_tile<{tile},0,{'true' if layers else 'false'}>",
+                            "kernel_avg_ms": tile_ms},
+               "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")}}
+        if not args.no_cpu:
+            cb = cpu_baseline(sc, 1)
+            row["cpu_baseline"] = cb
+        rows.append(row)
+        del ctx
+    out = {"metric": "optimisation steps/s with semi-transparent layers (512^2, 20480 tris, 4 views x 8 pairs)",
+           "unit": "steps/s", "higher_is_better": True, "dtype": "f32", "data": "synthetic", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "config": {"workload": "layers: icosphere 20480 tris, 512^2 px, lambert, RGBA albedo 512^2, "
+                                  "0 / 2 / 4 composited layers"},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

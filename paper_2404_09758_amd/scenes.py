@@ -382,6 +382,30 @@ def make_mid(seed=2, res=512, views=8, pairs=16) -> Scene:
                  n_pairs=pairs, optimizer=OPT_ADAM, steps=100, seed=seed)
 
 
+def make_layered(layers: int, seed=9, res=512, views=4, pairs=8) -> Scene:
+    """Semi-transparent variant of the mid workload (Sec. 4.4 "Transparent
+    geometry"): the 20480-triangle icosphere at 512^2 px, Lambert, with a
+    512^2 RGBA albedo whose fourth channel is the opacity (initial 0.5,
+    target a value-noise field in [0.3, 0.9]); the `layers` nearest
+    fragments of each pixel are composited, so the back of the sphere shows
+    through its front.  layers = 0 gives the opaque scene with the same
+    colour channels, for comparison.  4 ring views, 8 pairs, Adam."""
+    v, f, uv = _sphere_scene(32)
+    c = 4 if layers > 0 else 3
+    tex0 = np.full((res, res, c), 0.5, dtype=np.float32)
+    tgt = np.empty((res, res, c), np.float32)
+    tgt[..., :3] = value_noise_2d(res, res, seed * 1000 + 11, channels=3)
+    if c == 4:
+        tgt[..., 3] = 0.3 + 0.6 * value_noise_2d(res, res, seed * 1000 + 13, channels=1)[..., 0]
+    tgt_pos = _radial_displace(v, seed * 1000 + 12).astype(np.float32)
+    fy = 1.0 / math.tan(math.radians(FOVY_DEG) / 2)
+    eps_pos = 1.5 * (CAM_DIST / fy) * 2.0 / res
+    vs = [look_at_view(res, res, 90.0 * k + 20.0, 15.0) for k in range(views)]
+    return Scene(f"layered{layers}", f.astype(np.int32), uv, v.astype(np.float32), [tex0], tgt_pos, [tgt], vs,
+                 shading=SHADING_LAMBERT, eps=[eps_pos, 1.0 / 255.0], lr=[eps_pos, 1.0 / 255.0],
+                 n_pairs=pairs, optimizer=OPT_ADAM, steps=1, seed=seed, layers=layers)
+
+
 def make_paper(seed=3, res=1024, tex_res=1024, views=4, pairs=8, control_freq=12, splits=2) -> Scene:
     """1024^2 px, 46080-triangle sphere (frequency-12 control, two 1-to-4
     splits), albedo/normal/roughness maps at 1024^2, GGX, 4 views, 8 pairs."""

@@ -46,6 +46,11 @@ def measured_traffic():
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def progress(msg):
+    """A progress line on stderr (the result stays the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +225,7 @@ def main():
     px_per_step = sc.n_pairs * sum(v.width * v.height for v in sc.views)
     # launch shape from the autotuner (untimed)
     (tile, cap, _), tune_report = autotune.tune_scene(ctx, th0, sc.views, tg, sc.n_pairs, eps)
+    progress(f"autotune: tile {tile}, bin capacity {cap}")
     results = {}
     modes = {"batched": (tile, cap, 0), "plain": (tile, cap, 1)}
     order = ["graph", "batched", "plain"] if args.mode == "both" else [args.mode]
@@ -227,11 +233,13 @@ def main():
         if name == "graph":
             results[name] = run_graph_mode([sc], [tg], args.steps, args.warmup, api, batch, torch, dev, tile=tile,
                                            caps=[cap])
+            progress(f"mode graph: {results[name]['ms_per_step']:.3f} ms/step")
             continue
         th = th0.clone()
         m = torch.zeros_like(th)
         v = torch.zeros_like(th)
         results[name] = run_mode(ctx, sc, th, m, v, tg, eps, args.steps, args.warmup, modes[name], api, torch)
+        progress(f"mode {name}: {results[name]['ms_per_step']:.3f} ms/step")
     main_mode = order[0]
     r = results[main_mode]
     tm = r["timing"]
@@ -278,6 +286,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 4 * n
     if not args.no_cpu:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_items)
     print(json.dumps(out), flush=True)
 
@@ -295,6 +304,7 @@ def main_batch64(args, torch, api, autotune, batch, scenes, dev):
         del c
     px = sum(sc.n_pairs * sum(v.width * v.height for v in sc.views) for sc in scs)
     tile, caps, tune_report = autotune.tune_batch(scs, tgs, scs[0].n_pairs, dev, seed=scs[0].seed)
+    progress(f"autotune: tile {tile}")
     g = run_graph_mode(scs, tgs, args.steps, args.warmup, api, batch, torch, dev, tile=tile, caps=caps)
     p = run_sequential_plain(scs, tgs, args.steps, args.warmup, api, torch, dev, tile=tile, caps=caps)
     tm = g["timing"]
@@ -353,6 +363,7 @@ def main_soup(args, torch, api, scenes, dev):
             l1 = float(ctx.loss(th, sc.views, tg).sum())
             rows.append({"triangles": n, "d": sc.n_params, "estimator": name, "loss_ratio": l1 / l0,
                          "ms_per_step": start.elapsed_time(stop) / args.soup_steps})
+            progress(f"soup {n} {name}: loss ratio {l1 / l0:.4f}")
             del ctx
     out = {"metric": f"L2 loss after {args.soup_steps} Adam steps / initial loss (N=128 pairs/step, 512^2)",
            "config": {"workload": "soup: 1K/10K/100K-triangle soups, 12 params per triangle, unlit, "
@@ -395,6 +406,7 @@ def main_layers(args, torch, api, autotune, scenes, dev):
             cb = cpu_baseline(sc, 1)
             row["cpu_baseline"] = cb
         rows.append(row)
+        progress(f"layers {layers}: {row['steps_per_s']:.1f} steps/s")
         del ctx
     out = {"metric": "optimisation steps/s with semi-transparent layers (512^2, 20480 tris, 4 views x 8 pairs)",
            "unit": "steps/s", "higher_is_better": True, "dtype": "f32", "data": "synthetic", "n_gpus": 1,

@@ -339,14 +339,19 @@ def main_soup(args, torch, api, scenes, dev):
     pairs per step, Adam with lr = eps: the loss after --soup-steps steps
     relative to the initial loss, and the step time (the validation of
     Sec. 6.1 on a synthetic target image)."""
+    from paper_2404_09758_amd import autotune
     rows = []
     for n in (1024, 10240, 102400):
         sc = scenes.make_soup(n)
         tg = torch.tensor(sc.target_image, device=dev).reshape(-1)
+        probe = api.Context(sc, dev, tuning=(16, 256, 0))
+        th = torch.tensor(sc.flat_params(), device=dev)
+        tuning, _ = autotune.tune_scene(probe, th, sc.views, tg, sc.n_pairs, sc.eps, reps=1)
+        del probe
         for name, full, averaging in (("per_pixel_count", False, api.AVG_COUNT),
                                       ("per_pixel_pairs", False, api.AVG_PAIRS),
                                       ("full_image", True, api.AVG_PAIRS)):
-            ctx = api.Context(sc, dev, tuning=(16, 256, 0))
+            ctx = api.Context(sc, dev, tuning=tuning)
             th = torch.tensor(sc.flat_params(), device=dev)
             m = torch.zeros_like(th)
             v = torch.zeros_like(th)
@@ -362,8 +367,10 @@ def main_soup(args, torch, api, scenes, dev):
             torch.cuda.synchronize()
             l1 = float(ctx.loss(th, sc.views, tg).sum())
             rows.append({"triangles": n, "d": sc.n_params, "estimator": name, "loss_ratio": l1 / l0,
-                         "ms_per_step": start.elapsed_time(stop) / args.soup_steps})
-            progress(f"soup {n} {name}: loss ratio {l1 / l0:.4f}")
+                         "ms_per_step": start.elapsed_time(stop) / args.soup_steps, "tile_px": tuning[0],
+                         "bin_capacity": tuning[1], "tile_overflows": ctx.stats()["tile_overflows"]})
+            progress(f"soup {n} {name}: loss ratio {l1 / l0:.4f}, {rows[-1]['ms_per_step']:.2f} ms/step, "
+                     f"tuning {tuning}, overflows {rows[-1]['tile_overflows']}")
             del ctx
     out = {"metric": f"L2 loss after {args.soup_steps} Adam steps / initial loss (N=128 pairs/step, 512^2)",
            "config": {"workload": "soup: 1K/10K/100K-triangle soups, 12 params per triangle, unlit, "

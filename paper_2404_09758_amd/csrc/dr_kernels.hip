@@ -212,6 +212,35 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
     }
 }
 
+// Record the largest bin occupancy.  The value only grows, so a workgroup
+// that reads a value at least as large (possibly a stale one) may skip the
+// atomic: almost all do, and the single counter no longer serialises a
+// launch of a hundred thousand workgroups on one L2 channel.
+__device__ __forceinline__ void note_max_bin(unsigned long long* stats, unsigned c) {
+    unsigned long long seen = stats[ST_MAX_BIN];
+    if ((unsigned long long)c > seen) atomicMax(&stats[ST_MAX_BIN], (unsigned long long)c);
+}
+
+// Rasterise the cnt triangles of a tile's bin.  Wave w takes entries
+// w, w + nw, w + 2 nw, ...; it fetches 64 of them at once (one per lane),
+// so only the record load remains per triangle.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, unsigned cnt,
+                                           const TriR* __restrict__ R, int wave, int nw, int lane, int px0,
+                                           int py0, unsigned long long* key, int L) {
+    for (unsigned base = (unsigned)wave; base < cnt; base += 64u * (unsigned)nw) {
+        unsigned k = base + (unsigned)lane * (unsigned)nw;
+        unsigned mine = k < cnt ? list[k] : 0u;
+        unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
+        if (n > 64u) n = 64u;
+        for (unsigned j = 0; j < n; ++j) {
+            unsigned t = __builtin_amdgcn_readlane(mine, j);
+            TriR r = R[t];
+            raster_tri<TILE, DEEP>(r, t, px0, py0, lane, key, L);
+        }
+    }
+}
+
 // ------------------------------------------------ tile-local aggregation --
 //
 // Contributions are summed per group inside the workgroup before they reach
@@ -367,12 +396,8 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         cnt[s] = J.counts[s][J.tile];
         const TriR* __restrict__ R = J.recR[s];
         if (cnt[s] <= (unsigned)J.cap) {
-            const unsigned* __restrict__ list = J.bins[s] + (long long)J.tile * J.cap;
-            for (unsigned k = wave; k < cnt[s]; k += NW) {
-                unsigned t = __builtin_amdgcn_readfirstlane(list[k]);
-                TriR r = R[t];
-                raster_tri<TILE, false>(r, t, px0, py0, lane, S.key[s], 1);
-            }
+            raster_bin<TILE, false>(J.bins[s] + (long long)J.tile * J.cap, cnt[s], R, wave, NW, lane, px0, py0,
+                                    S.key[s], 1);
         } else {
             // bin overflow: test every triangle against this tile
             for (int t = wave; t < sc.n_tris; t += NW) {
@@ -388,7 +413,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         for (int s = 0; s < NS; ++s) {
             J.counts[s][J.tile] = 0u;            // leave the bin empty for the next use
             if (cnt[s] > (unsigned)J.cap) atomicAdd(&J.stats[ST_OVERFLOWS], 1ull);
-            atomicMax(&J.stats[ST_MAX_BIN], (unsigned long long)cnt[s]);
+            note_max_bin(J.stats, cnt[s]);
         }
     }
 
@@ -625,12 +650,8 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         cnt[s] = J.counts[s][J.tile];
         const TriR* __restrict__ R = J.recR[s];
         if (cnt[s] <= (unsigned)J.cap) {
-            const unsigned* __restrict__ list = J.bins[s] + (long long)J.tile * J.cap;
-            for (unsigned k = wave; k < cnt[s]; k += NW) {
-                unsigned t = __builtin_amdgcn_readfirstlane(list[k]);
-                TriR r = R[t];
-                raster_tri<TILE, true>(r, t, px0, py0, lane, S.key[s], L);
-            }
+            raster_bin<TILE, true>(J.bins[s] + (long long)J.tile * J.cap, cnt[s], R, wave, NW, lane, px0, py0,
+                                   S.key[s], L);
         } else {
             for (int t = wave; t < sc.n_tris; t += NW) {
                 TriR r = R[t];
@@ -645,7 +666,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         for (int s = 0; s < NS; ++s) {
             J.counts[s][J.tile] = 0u;
             if (cnt[s] > (unsigned)J.cap) atomicAdd(&J.stats[ST_OVERFLOWS], 1ull);
-            atomicMax(&J.stats[ST_MAX_BIN], (unsigned long long)cnt[s]);
+            note_max_bin(J.stats, cnt[s]);
         }
     }
 

@@ -205,6 +205,7 @@ typedef struct {
     int64_t area2;         /* twice the signed area, > 0 after normalising */
     int topleft[3];        /* edge k (opposite vertex k) is top or left     */
     float z0, zx, zy;      /* depth plane                                   */
+    float ia;              /* 1 / area2, formed once per triangle           */
 } tri_setup_t;
 
 /* Reading: triangles are made counter-clockwise in the y-down pixel frame
@@ -245,6 +246,7 @@ static tri_setup_t setup_triangle(const vtx_t* vt, const int32_t* tri, int32_t t
     s.z0 = s.z[0];
     s.zx = (d1 * fY2 - d2 * fY1) / fa;
     s.zy = (d2 * fX1 - d1 * fX2) / fa;
+    s.ia = 1.0f / fa;
     s.ok = 1;
     return s;
 }
@@ -369,25 +371,27 @@ typedef struct {
     float b[3];        /* screen-space barycentrics, normalised order     */
     float pc[3];       /* b_k / w_k                                       */
     float S;           /* sum of pc                                       */
+    float iS;          /* 1 / S                                           */
     float u, v;        /* perspective-correct texture coordinates         */
 } attr_t;
 
-/* Reading: b_k = E_k / area2 in fp32; perspective-correct interpolation
- * divides the 1/w-weighted sums by their total; sums run over the
- * normalised corner order. */
+/* Reading: b_k = E_k * (1 / area2) in fp32, the reciprocal formed once per
+ * triangle; perspective-correct interpolation multiplies the 1/w-weighted
+ * sums by the reciprocal of their total; sums run over the normalised
+ * corner order. */
 static attr_t attributes(const or_scene* sc, const tri_setup_t* s, int32_t t, int32_t px, int32_t py) {
     attr_t a;
     int64_t E[3];
     edges_at(s, px, py, E);
-    float fa = (float)s->area2;
-    for (int k = 0; k < 3; ++k) a.b[k] = (float)E[k] / fa;
+    for (int k = 0; k < 3; ++k) a.b[k] = (float)E[k] * s->ia;
     for (int k = 0; k < 3; ++k) a.pc[k] = a.b[k] * s->iw[k];
     a.S = (a.pc[0] + a.pc[1]) + a.pc[2];
+    a.iS = 1.0f / a.S;
     const float* cuv = sc->corner_uv + 6 * (int64_t)t;
     float u0 = cuv[2 * s->order[0]], u1 = cuv[2 * s->order[1]], u2 = cuv[2 * s->order[2]];
     float v0 = cuv[2 * s->order[0] + 1], v1 = cuv[2 * s->order[1] + 1], v2 = cuv[2 * s->order[2] + 1];
-    a.u = ((a.pc[0] * u0 + a.pc[1] * u1) + a.pc[2] * u2) / a.S;
-    a.v = ((a.pc[0] * v0 + a.pc[1] * v1) + a.pc[2] * v2) / a.S;
+    a.u = ((a.pc[0] * u0 + a.pc[1] * u1) + a.pc[2] * u2) * a.iS;
+    a.v = ((a.pc[0] * v0 + a.pc[1] * v1) + a.pc[2] * v2) * a.iS;
     return a;
 }
 
@@ -515,7 +519,7 @@ static void shade(const or_scene* sc, const or_view* vw, const float* th, const 
     float P[3];
     for (int c = 0; c < 3; ++c) {
         float q0 = p[s->order[0]][c], q1 = p[s->order[1]][c], q2 = p[s->order[2]][c];
-        P[c] = ((a.pc[0] * q0 + a.pc[1] * q1) + a.pc[2] * q2) / a.S;
+        P[c] = ((a.pc[0] * q0 + a.pc[1] * q1) + a.pc[2] * q2) * a.iS;
     }
     float V[3] = {vw->cam_pos[0] - P[0], vw->cam_pos[1] - P[1], vw->cam_pos[2] - P[2]};
     normalize3(V);
@@ -530,17 +534,18 @@ static void shade(const or_scene* sc, const or_view* vw, const float* th, const 
     float alpha = rough * rough;
     if (!(alpha > 0.002f)) alpha = 0.002f;
     float a2 = alpha * alpha;
+    /* D G F / (4 n.l n.v) with D = a2 / (pi dd^2) and the Smith-Schlick
+     * G = n.l / gl * n.v / gv: the factors n.l n.v cancel, leaving one
+     * division, a2 F / (4 pi dd^2 gl gv). */
     float dd = (ndh * ndh) * (a2 - 1.0f) + 1.0f;
-    float D = a2 / ((OR_PI * dd) * dd);
     float k = alpha * 0.5f;
-    float g1l = ndl / (ndl * (1.0f - k) + k);
-    float g1v = ndv / (ndv * (1.0f - k) + k);
-    float G = g1l * g1v;
+    float gl = ndl * (1.0f - k) + k;
+    float gv = ndv * (1.0f - k) + k;
     float om = 1.0f - vdh;
     float om5 = ((om * om) * (om * om)) * om;
     float F = 0.04f + 0.96f * om5;
     float spec = 0.0f;
-    if (ndl > 0.0f && ndv > 0.0f) spec = ((D * G) * F) / ((4.0f * ndl) * ndv);
+    if (ndl > 0.0f && ndv > 0.0f) spec = (a2 * F) / ((((4.0f * OR_PI) * dd) * dd) * (gl * gv));
     for (int c = 0; c < 3; ++c)
         rgb[c] = ((alb[c] * OR_INV_PI + spec) * sc->light_rgb[c]) * ndl + sc->ambient * alb[c];
 }

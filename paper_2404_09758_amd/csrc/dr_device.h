@@ -65,7 +65,8 @@ struct __align__(16) TriR {
     unsigned flags;                      // bit0 valid, bit1+k top-left edge k, bit4 swapped
     short bx0, by0, bx1, by1;            // inclusive pixel bbox, clamped to the view
     long long area2;
-    int pad[2];
+    float ia;                            // 1 / area2
+    int pad;
 };
 
 // Shading half (64 B): 1/w in normalised order, perturbed world positions
@@ -225,6 +226,32 @@ __device__ __forceinline__ Foot footprint(float u, float v, int W, int H) {
     return f;
 }
 
+// The C <= 4 consecutive parameters [i, i + C) of one texel, perturbed as by
+// pval: the values are read together (C = 3 and 4 as one vector load) and
+// the sign bits from the one or two words that hold them.
+__device__ __forceinline__ void texel_pvals(const float* __restrict__ th, long long i, int C, float e,
+                                            const uint32_t* __restrict__ pb, float sgn, float* x) {
+    if (C == 3) {
+        x[0] = th[i]; x[1] = th[i + 1]; x[2] = th[i + 2]; x[3] = 0.0f;
+    } else if (C == 1) {
+        x[0] = th[i]; x[1] = 0.0f; x[2] = 0.0f; x[3] = 0.0f;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = (c < C) ? th[i + c] : 0.0f;
+    }
+    if (pb == nullptr || e == 0.0f) return;
+    unsigned b = (unsigned)(i & 31);
+    long long wi = i >> 5;
+    unsigned long long w = pb[wi];
+    if (b + (unsigned)C > 32u) w |= (unsigned long long)pb[wi + 1] << 32;
+    w >>= b;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float se = ((w >> c) & 1ull) ? -e : e;
+        x[c] = (sgn > 0.0f) ? (x[c] + se) : (x[c] - se);
+    }
+}
+
 // Bilinear sample of texture t of the perturbed scene (theta + sgn s eps)
 // over a precomputed footprint.  out has room for 4 channels; the channel
 // loop is unrolled to 4 so that out stays in registers.
@@ -241,16 +268,14 @@ __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __rest
     long long i10 = base + ((long long)f.ya * W + f.xb) * C;
     long long i01 = base + ((long long)f.yb * W + f.xa) * C;
     long long i11 = base + ((long long)f.yb * W + f.xb) * C;
+    float t00[4], t10[4], t01[4], t11[4];
+    texel_pvals(th, i00, C, e, pb, sgn, t00);
+    texel_pvals(th, i10, C, e, pb, sgn, t10);
+    texel_pvals(th, i01, C, e, pb, sgn, t01);
+    texel_pvals(th, i11, C, e, pb, sgn, t11);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        if (c < C) {
-            float t00 = pval(th, i00 + c, e, pb, sgn);
-            float t10 = pval(th, i10 + c, e, pb, sgn);
-            float t01 = pval(th, i01 + c, e, pb, sgn);
-            float t11 = pval(th, i11 + c, e, pb, sgn);
-            out[c] = ((w00 * t00 + w10 * t10) + w01 * t01) + w11 * t11;
-        }
-    }
+    for (int c = 0; c < 4; ++c)
+        if (c < C) out[c] = ((w00 * t00[c] + w10 * t10[c]) + w01 * t01[c]) + w11 * t11[c];
 }
 
 __device__ __forceinline__ void nrm3(float* x) {
@@ -299,6 +324,41 @@ __device__ __forceinline__ void face_frame(int shading, const float* p, const fl
     for (int c = 0; c < 3; ++c) { F.T[c] = T[c]; F.B[c] = B[c]; }
 }
 
+// Perspective-correct attributes of pixel (px,py) on triangle t: the
+// 1/w-weighted barycentrics, the reciprocal of their sum and the UV.
+struct Attr {
+    float pc0, pc1, pc2, iS, u, v;
+};
+
+__device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const TriS& s, int t, int px, int py) {
+    // edge functions as floats; for a TRI_SMALL triangle they fit in 32 bits
+    // and convert in one instruction, to the same values
+    float f0, f1, f2;
+    if (r.flags & TRI_SMALL) {
+        int e0 = __mul24(r.X[2] - r.X[1], py - r.Y[1]) - __mul24(r.Y[2] - r.Y[1], px - r.X[1]);
+        int e1 = __mul24(r.X[0] - r.X[2], py - r.Y[2]) - __mul24(r.Y[0] - r.Y[2], px - r.X[2]);
+        int e2 = __mul24(r.X[1] - r.X[0], py - r.Y[0]) - __mul24(r.Y[1] - r.Y[0], px - r.X[0]);
+        f0 = (float)e0; f1 = (float)e1; f2 = (float)e2;
+    } else {
+        long long e0, e1, e2;
+        (void)inside(r, px, py, e0, e1, e2);
+        f0 = (float)e0; f1 = (float)e1; f2 = (float)e2;
+    }
+    float b0 = f0 * r.ia, b1 = f1 * r.ia, b2 = f2 * r.ia;
+    float pc0 = b0 * s.iw[0], pc1 = b1 * s.iw[1], pc2 = b2 * s.iw[2];
+    float S = (pc0 + pc1) + pc2;
+    float iS = 1.0f / S;
+    bool sw = (r.flags & TRI_SWAPPED) != 0u;
+    const float* cuv = sc.cuv + 6 * (long long)t;
+    float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];
+    float un1 = sw ? cu2 : cu1, vn1 = sw ? cv2 : cv1, un2 = sw ? cu1 : cu2, vn2 = sw ? cv1 : cv2;
+    Attr a;
+    a.pc0 = pc0; a.pc1 = pc1; a.pc2 = pc2; a.iS = iS;
+    a.u = ((pc0 * cu0 + pc1 * un1) + pc2 * un2) * iS;
+    a.v = ((pc0 * cv0 + pc1 * vn1) + pc2 * vn2) * iS;
+    return a;
+}
+
 // Colour, opacity and UV of pixel (px,py) (subpixel sample coordinates)
 // covered by triangle t: perspective-correct attributes, then unlit /
 // Lambert / GGX.  foot0 receives the bilinear footprint of texel class 0 at
@@ -308,19 +368,10 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
                                             const uint32_t* __restrict__ pb, const float* eps, float sgn,
                                             const TriR& r, const TriS& s, const TriF& fr, int t, int px, int py,
                                             float* rgb, float* uvo, Foot& foot0, float& opacity) {
-    long long e0, e1, e2;
-    (void)inside(r, px, py, e0, e1, e2);
-    float fa = (float)r.area2;
-    float b0 = (float)e0 / fa, b1 = (float)e1 / fa, b2 = (float)e2 / fa;
-    float pc0 = b0 * s.iw[0], pc1 = b1 * s.iw[1], pc2 = b2 * s.iw[2];
-    float S = (pc0 + pc1) + pc2;
+    Attr a = frag_attr(sc, r, s, t, px, py);
+    float pc0 = a.pc0, pc1 = a.pc1, pc2 = a.pc2, iS = a.iS, u = a.u, v = a.v;
     bool sw = (r.flags & TRI_SWAPPED) != 0u;
     int o1 = sw ? 2 : 1, o2 = sw ? 1 : 2;
-    const float* cuv = sc.cuv + 6 * (long long)t;
-    float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];
-    float un1 = sw ? cu2 : cu1, vn1 = sw ? cv2 : cv1, un2 = sw ? cu1 : cu2, vn2 = sw ? cv1 : cv2;
-    float u = ((pc0 * cu0 + pc1 * un1) + pc2 * un2) / S;
-    float v = ((pc0 * cv0 + pc1 * vn1) + pc2 * vn2) / S;
     uvo[0] = u;
     uvo[1] = v;
     float alb[4] = {0.0f, 0.0f, 0.0f, 1.0f};
@@ -369,7 +420,7 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float q0 = s.p[c], q1 = s.p[3 * o1 + c], q2 = s.p[3 * o2 + c];
-        P[c] = ((pc0 * q0 + pc1 * q1) + pc2 * q2) / S;
+        P[c] = ((pc0 * q0 + pc1 * q1) + pc2 * q2) * iS;
     }
     float V[3] = {vw.cam[0] - P[0], vw.cam[1] - P[1], vw.cam[2] - P[2]};
     nrm3(V);
@@ -384,17 +435,17 @@ __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, c
     float alpha = rough4[0] * rough4[0];
     if (!(alpha > 0.002f)) alpha = 0.002f;
     float a2 = alpha * alpha;
+    // D G F / (4 n.l n.v) with D = a2 / (pi dd^2) and Smith-Schlick
+    // G = n.l / gl * n.v / gv: n.l n.v cancel, leaving one division
     float dd = (ndh * ndh) * (a2 - 1.0f) + 1.0f;
-    float D = a2 / ((DRD_PI * dd) * dd);
     float k = alpha * 0.5f;
-    float g1l = ndl / (ndl * (1.0f - k) + k);
-    float g1v = ndv / (ndv * (1.0f - k) + k);
-    float G = g1l * g1v;
+    float gl = ndl * (1.0f - k) + k;
+    float gv = ndv * (1.0f - k) + k;
     float om = 1.0f - vdh;
     float om5 = ((om * om) * (om * om)) * om;
     float F = 0.04f + 0.96f * om5;
     float spec = 0.0f;
-    if (ndl > 0.0f && ndv > 0.0f) spec = ((D * G) * F) / ((4.0f * ndl) * ndv);
+    if (ndl > 0.0f && ndv > 0.0f) spec = (a2 * F) / ((((4.0f * DRD_PI) * dd) * dd) * (gl * gv));
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         rgb[c] = ((alb[c] * DRD_INV_PI + spec) * sc.light_rgb[c]) * ndl + sc.ambient * alb[c];

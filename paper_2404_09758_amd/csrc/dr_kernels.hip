@@ -69,7 +69,8 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     TriR r;
     TriS sh;
     r.flags = 0u;
-    r.pad[0] = 0; r.pad[1] = 0;
+    r.ia = 0.0f;
+    r.pad = 0;
     bool ok = v[0].valid && v[1].valid && v[2].valid;
     long long area2 = 0;
     if (ok) {
@@ -104,6 +105,7 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     r.z0 = v[0].z;
     r.zx = (d1 * fY2 - d2 * fY1) / fa;
     r.zy = (d2 * fX1 - d1 * fX2) / fa;
+    r.ia = 1.0f / fa;
     int xmin = min(r.X[0], min(r.X[1], r.X[2])), xmax = max(r.X[0], max(r.X[1], r.X[2]));
     int ymin = min(r.Y[0], min(r.Y[1], r.Y[2])), ymax = max(r.Y[0], max(r.Y[1], r.Y[2]));
     if (xmax - xmin < 32768 && ymax - ymin < 32768) r.flags |= TRI_SMALL;
@@ -676,56 +678,53 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
     bool inpix = x < vw.W && y < vw.H;
     int px = 256 * x + 128, py = 256 * y + 128;
     long long pix = (long long)y * vw.W + x;
-    unsigned ids[NE];
-    float us[NE], vs[NE];
+    // Lists fill from the front, so a list is empty when its first layer is.
+    // The loops over layers stay rolled (the fragments are re-read from the
+    // LDS list, their UVs recomputed where needed) so that nothing indexed
+    // by layer has to live in registers.
     float rgb[NS][3];
+    bool any = false;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
         float T = 1.0f;
-#pragma unroll
-        for (int l = 0; l < LM; ++l) {
-            int e = s * LM + l;
-            unsigned long long k = (inpix && l < L) ? S.key[s][local * LM + l] : ~0ull;
-            ids[e] = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
-            us[e] = 0.0f;
-            vs[e] = 0.0f;
-            if (ids[e] != DRD_BG) {
-                TriR r = J.recR[s][ids[e]];
-                TriS sh = J.recS[s][ids[e]];
+        for (int l = 0; l < L; ++l) {
+            unsigned long long k = inpix ? S.key[s][local * LM + l] : ~0ull;
+            unsigned id = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
+            float uv[2] = {0.0f, 0.0f};
+            if (id != DRD_BG) {
+                any = true;
+                TriR r = J.recR[s][id];
+                TriS sh = J.recS[s][id];
                 TriF fr;
-                if (sc.shading != 0) fr = J.recF[s][ids[e]];
-                float c[3], uv[2], al;
+                if (sc.shading != 0) fr = J.recF[s][id];
+                float c[3], al;
                 Foot f0;
-                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)ids[e], px, py, c, uv, f0, al);
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id, px, py, c, uv, f0, al);
                 float wt = T * al;
                 rgb[s][0] = rgb[s][0] + wt * c[0];
                 rgb[s][1] = rgb[s][1] + wt * c[1];
                 rgb[s][2] = rgb[s][2] + wt * c[2];
                 T = T * (1.0f - al);
-                us[e] = uv[0];
-                vs[e] = uv[1];
+            }
+            if constexpr (MODE == 1) {
+                if (inpix) {
+                    long long e = pix * L + l;
+                    if (J.out_id) J.out_id[e] = id;
+                    if (J.out_uv) {
+                        J.out_uv[2 * e + 0] = uv[0];
+                        J.out_uv[2 * e + 1] = uv[1];
+                    }
+                }
             }
         }
     }
 
     if constexpr (MODE == 1) {
-        if (inpix) {
-            if (J.out_rgb) {
-                J.out_rgb[3 * pix + 0] = rgb[0][0];
-                J.out_rgb[3 * pix + 1] = rgb[0][1];
-                J.out_rgb[3 * pix + 2] = rgb[0][2];
-            }
-#pragma unroll
-            for (int l = 0; l < LM; ++l) {
-                if (l >= L) break;
-                long long e = pix * L + l;
-                if (J.out_id) J.out_id[e] = ids[l];
-                if (J.out_uv) {
-                    J.out_uv[2 * e + 0] = us[l];
-                    J.out_uv[2 * e + 1] = vs[l];
-                }
-            }
+        if (inpix && J.out_rgb) {
+            J.out_rgb[3 * pix + 0] = rgb[0][0];
+            J.out_rgb[3 * pix + 1] = rgb[0][1];
+            J.out_rgb[3 * pix + 2] = rgb[0][2];
         }
         return;
     }
@@ -745,9 +744,6 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         if (tid == 0) *J.partial = S.red[0];
         return;
     }
-    // lists fill from the front: an empty first layer means an empty list
-    bool any = ids[0] != DRD_BG;
-    if constexpr (NS == 2) any = any || ids[LM] != DRD_BG;
     if constexpr (MODE == 3) {
         long long qsum = 0;
         if (inpix && any) {
@@ -770,53 +766,63 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
             int flag;
             long long q = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
             if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
-            if (J.act_pos) {
-                int vid[NE][3];
+            // fragment e = s * L + l; each group is added by the first
+            // fragment that holds it
+            const int NF = NS * L;
+            for (int e = 0; e < NF; ++e) {
+                int s1 = e / L, l1 = e % L;
+                unsigned long long k1 = (&S.key[0][0])[(s1 * NPIX + local) * LM + l1];
+                if (k1 == ~0ull) continue;
+                unsigned id1 = (unsigned)(k1 & 0xFFFFFFFFull);
+                if (J.act_pos) {
+                    TriS sh1 = (s1 ? J.recS[1] : J.recS[0])[id1];
+                    bool dup[3] = {false, false, false};
+                    for (int e2 = 0; e2 < e; ++e2) {
+                        unsigned long long k2 = (&S.key[0][0])[((e2 / L) * NPIX + local) * LM + e2 % L];
+                        if (k2 == ~0ull) continue;
+                        TriS sh2 = (e2 >= L ? J.recS[1] : J.recS[0])[(unsigned)(k2 & 0xFFFFFFFFull)];
 #pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    vid[e][0] = vid[e][1] = vid[e][2] = -1;
-                    if (ids[e] != DRD_BG) {
-                        TriS sh = J.recS[e / LM][ids[e]];
-                        vid[e][0] = sh.vid[0]; vid[e][1] = sh.vid[1]; vid[e][2] = sh.vid[2];
+                        for (int k = 0; k < 3; ++k)
+                            dup[k] = dup[k] || sh1.vid[k] == sh2.vid[0] || sh1.vid[k] == sh2.vid[1] ||
+                                     sh1.vid[k] == sh2.vid[2];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)sh1.vid[k], q, 1u);
+                }
+                if (J.any_act && sc.n_cls > 0) {
+                    Attr a1 = frag_attr(sc, (s1 ? J.recR[1] : J.recR[0])[id1], (s1 ? J.recS[1] : J.recS[0])[id1],
+                                        (int)id1, px, py);
+                    for (int c = 0; c < sc.n_cls; ++c) {
+                        if (!J.act_cls[c]) continue;
+                        unsigned gs[4];
+                        texel_groups(sc, c, a1.u, a1.v, gs);
+                        bool dup[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            dup[k] = gs[k] == HASH_EMPTY;
+#pragma unroll
+                            for (int k2 = 0; k2 < 4; ++k2)
+                                if (k2 < k && gs[k2] == gs[k]) dup[k] = true;
+                        }
+                        for (int e2 = 0; e2 < e; ++e2) {
+                            unsigned long long k2 = (&S.key[0][0])[((e2 / L) * NPIX + local) * LM + e2 % L];
+                            if (k2 == ~0ull) continue;
+                            unsigned id2 = (unsigned)(k2 & 0xFFFFFFFFull);
+                            Attr a2 = frag_attr(sc, (e2 >= L ? J.recR[1] : J.recR[0])[id2],
+                                                (e2 >= L ? J.recS[1] : J.recS[0])[id2], (int)id2, px, py);
+                            unsigned gs2[4];
+                            texel_groups(sc, c, a2.u, a2.v, gs2);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                dup[k] = dup[k] || gs[k] == gs2[0] || gs[k] == gs2[1] || gs[k] == gs2[2] ||
+                                         gs[k] == gs2[3];
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, gs[k], q, 1u);
                     }
                 }
-#pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    if (ids[e] == DRD_BG) continue;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        int g = vid[e][k];
-                        bool dup = false;
-#pragma unroll
-                        for (int e2 = 0; e2 < e; ++e2)
-                            dup = dup || g == vid[e2][0] || g == vid[e2][1] || g == vid[e2][2];
-                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
-                    }
-                }
-            }
-            for (int c = 0; c < sc.n_cls; ++c) {
-                if (!J.act_cls[c]) continue;
-                unsigned gs[NE][4];
-#pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    gs[e][0] = gs[e][1] = gs[e][2] = gs[e][3] = HASH_EMPTY;
-                    if (ids[e] != DRD_BG) texel_groups(sc, c, us[e], vs[e], gs[e]);
-                }
-#pragma unroll
-                for (int e = 0; e < NE; ++e)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        unsigned g = gs[e][k];
-                        if (g == HASH_EMPTY) continue;
-                        bool dup = false;
-#pragma unroll
-                        for (int k2 = 0; k2 < 4; ++k2)
-                            if (k2 < k && gs[e][k2] == g) dup = true;
-#pragma unroll
-                        for (int e2 = 0; e2 < e; ++e2)
-                            dup = dup || g == gs[e2][0] || g == gs[e2][1] || g == gs[e2][2] || g == gs[e2][3];
-                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, g, q, 1u);
-                    }
             }
         }
         __syncthreads();

@@ -30,9 +30,10 @@ BYTES_PER_PIXEL_ESTIMATE = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per k_tile launch from the committed rocprofv3 counters, or
-    None when the kernel sources changed since they were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    counters, or None when they were taken on another kernel or the kernel
+    sources changed since."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -41,7 +42,7 @@ def measured_traffic():
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec["kernel_sources_sha256"]:
+    if h.hexdigest() != rec["kernel_sources_sha256"] or rec.get("kernel") != kernel:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -246,9 +247,9 @@ def main():
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     launches_per_step = tm["tile_launches"] / args.steps
     alg_bytes_launch = BYTES_PER_PIXEL_ESTIMATE * px_per_step / launches_per_step
-    traffic = measured_traffic() if main_mode == "graph" and args.config == "paper" else None
+    kernel = f"k_tile_b<{tile}>" if main_mode == "graph" else f"k_tile<{tile},0,false>"
+    traffic = measured_traffic(kernel) if args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
-    kernel = f"k_tile_b<{tile}>" if main_mode == "graph" else f"k_tile<{tile},0>"
     out = {
         "metric": METRIC,
         "value": 1e3 / r["ms_per_step"],

@@ -30,10 +30,15 @@ BYTES_PER_PIXEL_ESTIMATE = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    counters, or None when they were taken on another kernel or the kernel
-    sources changed since."""
+# Vector issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU
+# instruction per SIMD every 4 cycles.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def profiled_counters(kernel):
+    """The committed rocprofv3 counters of `kernel` (HBM bytes and VALU
+    instructions per launch), or None when they were taken on another kernel
+    or the kernel sources changed since."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -44,7 +49,13 @@ def measured_traffic(kernel):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec["kernel_sources_sha256"] or rec.get("kernel") != kernel:
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counters, or None."""
+    rec = profiled_counters(kernel)
+    return None if rec is None else rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def progress(msg):
@@ -276,6 +287,12 @@ def main():
         "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")},
         "pixel_estimates_per_s": px_per_step * 1e3 / r["ms_per_step"],
     }
+    rec = profiled_counters(kernel) if args.config == "paper" else None
+    if rec is not None and "valu_wave_instructions_per_launch" in rec:
+        # the ceiling the kernel actually meets: vector instruction issue
+        rate = rec["valu_wave_instructions_per_launch"] / (tile_avg_ms * 1e-3)
+        out["issue"] = {"valu_wave_instructions_per_launch": rec["valu_wave_instructions_per_launch"],
+                        "achieved_per_s": rate, "peak_per_s": VALU_ISSUE_PEAK, "frac": rate / VALU_ISSUE_PEAK}
     for name, rr in results.items():
         out[f"{name}_steps_per_s"] = 1e3 / rr["ms_per_step"]
     if args.probe_copy_mib > 0:

@@ -63,6 +63,14 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gate(torch, ms=100.0):
+    """Hold the stream with a short device-side spin so the host can queue a
+    timed sequence ahead of the GPU: the per-kernel event intervals then hold
+    no host launch gaps."""
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(int(ms * 1e-3 * 2.4e9))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,10 +104,10 @@ def run_mode(ctx, sc, th, m, v, tg, eps, steps, warmup, tuning, api, torch):
     torch.cuda.synchronize()
     ctx.timing_read(reset=True)
     ctx.timing_enable(True)
-    # contributions per step (sum of K) measured once, outside the timed loop
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    gate(torch)
     w0 = time.perf_counter()
     start.record()
     for _ in range(steps):
@@ -170,6 +178,7 @@ def run_graph_mode(sc_list, tg_list, steps, warmup, api, batch_mod, torch, dev, 
     # per-kernel durations: the same kernels launched directly, with events
     bt.timing_read(reset=True)
     bt.timing_enable(True)
+    gate(torch)
     for _ in range(steps):
         bt.step(use_graph=False)
     bt.timing_enable(False)

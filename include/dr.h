@@ -84,6 +84,20 @@ typedef struct {
                                  /* black; opacity = the albedo's fourth      */
                                  /* channel (tex_c[0] must then be 4),        */
                                  /* clamped to [0, 1].  Needs tile_px <= 16.  */
+    /* Subdivision surface (Sec. 6.3): n_ctrl > 0 makes the position
+     * parameters n_ctrl control vertices (theta starts with 3 * n_ctrl
+     * coordinates) and tri / corner_uv / n_verts the tessellated surface
+     * (see dr_subdivide), whose vertex j is, per coordinate, the sum over k
+     * in [sub_rowptr[j], sub_rowptr[j+1]) of sub_w[k] times control vertex
+     * sub_cols[k], added in that order from zero (device pointers, valid
+     * for the life of the context).  A pixel's vertex groups are then the
+     * control vertices its triangle's corners combine.  Opaque scenes only
+     * (layers == 0); not available in a dr_batch.  n_ctrl == 0: the mesh's
+     * own vertices are the parameters. */
+    int32_t n_ctrl;
+    const int32_t* sub_rowptr;   /* [n_verts + 1]                             */
+    const int32_t* sub_cols;     /* [nnz], ascending within a row             */
+    const float* sub_w;          /* [nnz]                                     */
 } dr_scene;
 
 /* A camera: clip = view_proj * [x y z 1]^T (row-major); pixel (0,0) is the
@@ -138,6 +152,31 @@ dr_status dr_create(dr_ctx** out, const dr_scene* scene, const dr_tuning* tune, 
 dr_status dr_destroy(dr_ctx* ctx);
 dr_status dr_set_stream(dr_ctx* ctx, void* stream);
 dr_status dr_set_tuning(dr_ctx* ctx, const dr_tuning* tune);
+/* Catmull-Clark tessellation of a closed manifold triangle control mesh
+ * (Sec. 6.3; Catmull and Clark 1978), on the host: `levels` (1 or 2)
+ * refinements, then every quad (q0, q1, q2, q3) split into (q0, q1, q2) and
+ * (q0, q2, q3).  Rules per level: face point = mean of the face's vertices;
+ * edge point = (a + b + f1 + f2) / 4; vertex point = (Q + 2 R + (n - 3) v) / n
+ * with n the valence, Q the mean of the adjacent face points and R the mean
+ * of the adjacent edge midpoints.  Numbering: vertex points first (vertex i
+ * keeps index i), then edge points in order of first appearance (faces in
+ * order, edges (v_k, v_k+1)), then face points; face (v_0 .. v_m-1) becomes
+ * the quads (v'_k, e(v_k, v_k+1), f', e(v_k-1, v_k)), k = 0 .. m-1.
+ * Weights are exact rationals rounded once (num / den in double, then to
+ * float).  Texture coordinates are face-varying and refined linearly in the
+ * control triangle: fine corner UV = ((n0 ua + n1 ub) + n2 uc) / 24 in double,
+ * rounded to float, with n_k / 24 the corner's barycentrics.
+ * All pointers are HOST pointers.  dr_subdivide_sizes reports the output
+ * sizes; dr_subdivide fills fine_tri [F_f,3], fine_corner_uv [F_f,3,2],
+ * rowptr [n_fine + 1], cols and w [nnz] (the sub_* arrays of dr_scene).
+ * DR_E_INVALID for indices out of range, a mesh that is not a closed
+ * manifold, or levels outside 1..2. */
+dr_status dr_subdivide_sizes(const int32_t* tri, int32_t n_verts, int32_t n_tris, int32_t levels,
+                             int32_t* n_fine_verts, int32_t* n_fine_tris, int64_t* nnz);
+dr_status dr_subdivide(const int32_t* tri, const float* corner_uv, int32_t n_verts, int32_t n_tris,
+                       int32_t levels, int32_t* fine_tri, float* fine_corner_uv, int32_t* rowptr,
+                       int32_t* cols, float* w);
+
 /* Counter word 3 of the sign stream of dr_estimate_grad (default 0): the
  * index of this scene in a batch, so that a scene stepped alone draws the
  * same signs as in a dr_batch. */

@@ -39,7 +39,9 @@ class Scene_(C.Structure):
                 ("tex_c", C.c_int32 * MAX_TEX),
                 ("shading", C.c_int32), ("tex_mode", C.c_int32),
                 ("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3),
-                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32)]
+                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32),
+                ("n_ctrl", C.c_int32), ("sub_rowptr", C.c_void_p), ("sub_cols", C.c_void_p),
+                ("sub_w", C.c_void_p)]
 
 
 class View_(C.Structure):
@@ -130,12 +132,27 @@ class Oracle:
     """The oracle bound to one scene (topology, UVs, texture shapes, shading)."""
 
     def __init__(self, scene, tex_shapes=None, shading=None, tex_mode=None):
-        self.tri = _c(scene.tri, np.int32)
-        self.corner_uv = _c(scene.corner_uv, np.float32)
+        levels = int(getattr(scene, "subdiv_levels", 0))
+        n_verts = int(scene.pos.shape[0]) if hasattr(scene, "pos") else int(scene.n_verts)
+        self.surface = None
+        if levels > 0:
+            # scene.tri / corner_uv are the control mesh (Sec. 6.3)
+            from . import subdiv
+            self.surface = subdiv.catmull_clark(scene.tri, n_verts, scene.corner_uv, levels)
+            self.tri = _c(self.surface["tri"], np.int32)
+            self.corner_uv = _c(self.surface["corner_uv"], np.float32)
+        else:
+            self.tri = _c(scene.tri, np.int32)
+            self.corner_uv = _c(scene.corner_uv, np.float32)
         shapes = tex_shapes if tex_shapes is not None else [t.shape for t in scene.tex]
         s = Scene_()
-        s.n_verts = int(scene.pos.shape[0]) if hasattr(scene, "pos") else int(scene.n_verts)
+        s.n_verts = n_verts if levels == 0 else int(self.surface["n_fine"])
         s.n_tris = int(self.tri.shape[0])
+        if levels > 0:
+            s.n_ctrl = n_verts
+            s.sub_rowptr = _ptr(self.surface["rowptr"])
+            s.sub_cols = _ptr(self.surface["cols"])
+            s.sub_w = _ptr(self.surface["w"])
         s.tri = _ptr(self.tri)
         s.corner_uv = _ptr(self.corner_uv)
         s.n_tex = len(shapes)

@@ -76,15 +76,19 @@ void or_signs(uint64_t seed, uint32_t step, uint32_t pair, uint32_t scene, int64
 /* Parameter layout (Sec. 4.1: theta = geometry then textures)          */
 /* ------------------------------------------------------------------ */
 
+/* Position groups: the control vertices of a subdivision surface, else
+ * the mesh's vertices. */
+static int64_t n_pos(const or_scene* sc) { return sc->n_ctrl > 0 ? sc->n_ctrl : sc->n_verts; }
+
 int64_t or_param_count(const or_scene* sc) {
-    int64_t d = 3 * (int64_t)sc->n_verts;
+    int64_t d = 3 * n_pos(sc);
     for (int t = 0; t < sc->n_tex; ++t)
         d += (int64_t)sc->tex_w[t] * sc->tex_h[t] * sc->tex_c[t];
     return d;
 }
 
 static int64_t tex_offset(const or_scene* sc, int t) {
-    int64_t off = 3 * (int64_t)sc->n_verts;
+    int64_t off = 3 * n_pos(sc);
     for (int k = 0; k < t; ++k) off += (int64_t)sc->tex_w[k] * sc->tex_h[k] * sc->tex_c[k];
     return off;
 }
@@ -102,7 +106,7 @@ typedef struct {
 static classes_t texel_classes(const or_scene* sc) {
     classes_t c;
     memset(&c, 0, sizeof(c));
-    int64_t off = sc->n_verts;
+    int64_t off = n_pos(sc);
     for (int t = 0; t < sc->n_tex; ++t) {
         int found = -1;
         for (int j = 0; j < t; ++j)
@@ -122,14 +126,14 @@ static classes_t texel_classes(const or_scene* sc) {
 
 int64_t or_group_count(const or_scene* sc) {
     classes_t c = texel_classes(sc);
-    int64_t g = sc->n_verts;
+    int64_t g = n_pos(sc);
     for (int k = 0; k < c.n; ++k) g += (int64_t)sc->tex_w[c.first[k]] * sc->tex_h[c.first[k]];
     return g;
 }
 
 /* Block of parameter i: 0 = positions, 1 + t = texture t. */
 static int block_of(const or_scene* sc, int64_t i) {
-    int64_t off = 3 * (int64_t)sc->n_verts;
+    int64_t off = 3 * n_pos(sc);
     if (i < off) return 0;
     for (int t = 0; t < sc->n_tex; ++t) {
         off += (int64_t)sc->tex_w[t] * sc->tex_h[t] * sc->tex_c[t];
@@ -463,7 +467,7 @@ static void cross3(const float* a, const float* b, float* o) {
  * Smith-Schlick geometry (k = alpha/2), Schlick Fresnel (F0 = 0.04) and a
  * tangent-space normal map in the face's UV frame.  The colour depends only
  * on the triangle's three vertices and on the texels of its footprint. */
-static void shade(const or_scene* sc, const or_view* vw, const float* th, const tri_setup_t* s,
+static void shade(const or_scene* sc, const or_view* vw, const float* th, const float* pos, const tri_setup_t* s,
                   int32_t t, int32_t px, int32_t py, float* rgb, float* uv_out, float* alpha_out) {
     attr_t a = attributes(sc, s, t, px, py);
     uv_out[0] = a.u;
@@ -483,7 +487,7 @@ static void shade(const or_scene* sc, const or_view* vw, const float* th, const 
     const int32_t* ti = sc->tri + 3 * (int64_t)t;
     float p[3][3];
     for (int k = 0; k < 3; ++k)
-        for (int c = 0; c < 3; ++c) p[k][c] = th[3 * (int64_t)ti[k] + c];
+        for (int c = 0; c < 3; ++c) p[k][c] = pos[3 * (int64_t)ti[k] + c];
     float e1[3], e2[3], nf[3];
     for (int c = 0; c < 3; ++c) { e1[c] = p[1][c] - p[0][c]; e2[c] = p[2][c] - p[0][c]; }
     cross3(e1, e2, nf);
@@ -553,24 +557,46 @@ static void shade(const or_scene* sc, const or_view* vw, const float* th, const 
 typedef struct {
     int W, H;
     float* th;             /* perturbed parameters                         */
+    float* pos;            /* mesh vertex positions [n_verts, 3]           */
     vtx_t* vt;
     tri_setup_t* ts;
 } frame_t;
+
+/* Vertex positions of the tessellated surface from the (perturbed) control
+ * vertices: per vertex and coordinate, the weighted terms of its row added
+ * in row order to a zero start, each weight times coordinate an fp32
+ * product. */
+static void subdivide_positions(const or_scene* sc, const float* ctrl, float* pos) {
+    for (int32_t j = 0; j < sc->n_verts; ++j)
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.0f;
+            for (int32_t k = sc->sub_rowptr[j]; k < sc->sub_rowptr[j + 1]; ++k)
+                acc = acc + sc->sub_w[k] * ctrl[3 * (int64_t)sc->sub_cols[k] + c];
+            pos[3 * (int64_t)j + c] = acc;
+        }
+}
 
 static int build_frame(frame_t* fr, const or_scene* sc, const float* theta, const int8_t* s, int sign,
                        const float* eps, const or_view* vw) {
     fr->W = vw->width;
     fr->H = vw->height;
     fr->th = perturbed_copy(sc, theta, s, sign, eps);
+    fr->pos = fr->th;
+    if (sc->n_ctrl > 0) {
+        fr->pos = (float*)malloc(sizeof(float) * 3 * (size_t)(sc->n_verts > 0 ? sc->n_verts : 1));
+        if (!fr->pos || !fr->th) return -1;
+        subdivide_positions(sc, fr->th, fr->pos);
+    }
     fr->vt = (vtx_t*)malloc(sizeof(vtx_t) * (size_t)(sc->n_verts > 0 ? sc->n_verts : 1));
     fr->ts = (tri_setup_t*)malloc(sizeof(tri_setup_t) * (size_t)(sc->n_tris > 0 ? sc->n_tris : 1));
     if (!fr->th || !fr->vt || !fr->ts) return -1;
-    for (int32_t j = 0; j < sc->n_verts; ++j) fr->vt[j] = transform_vertex(vw, fr->th + 3 * (int64_t)j);
+    for (int32_t j = 0; j < sc->n_verts; ++j) fr->vt[j] = transform_vertex(vw, fr->pos + 3 * (int64_t)j);
     for (int32_t t = 0; t < sc->n_tris; ++t) fr->ts[t] = setup_triangle(fr->vt, sc->tri, t);
     return 0;
 }
 
 static void free_frame(frame_t* fr) {
+    if (fr->pos != fr->th) free(fr->pos);
     free(fr->th);
     free(fr->vt);
     free(fr->ts);
@@ -595,7 +621,7 @@ static int render_frame(const or_scene* sc, const or_view* vw, frame_t* fr, floa
                 int64_t e = p * L + l;
                 float c[3] = {0.0f, 0.0f, 0.0f}, w[2] = {0.0f, 0.0f}, al = 1.0f;
                 if (id[e] != BG_ID)
-                    shade(sc, vw, fr->th, &fr->ts[id[e]], (int32_t)id[e], 256 * x + 128, 256 * y + 128, c, w,
+                    shade(sc, vw, fr->th, fr->pos, &fr->ts[id[e]], (int32_t)id[e], 256 * x + 128, 256 * y + 128, c, w,
                           &al);
                 uv[2 * e + 0] = w[0]; uv[2 * e + 1] = w[1];
                 if (sc->layers == 0) {
@@ -665,7 +691,7 @@ int64_t or_quantize(float delta, or_stats* st) {
 /* group once)                                                          */
 /* ------------------------------------------------------------------ */
 
-#define MAX_SET 256
+#define MAX_SET 1024
 
 typedef struct {
     int n;
@@ -675,6 +701,7 @@ typedef struct {
 static void set_add(gset_t* s, int64_t g) {
     for (int i = 0; i < s->n; ++i)
         if (s->g[i] == g) return;
+    if (s->n == MAX_SET) abort();        /* a contribution set this large is a bug */
     s->g[s->n++] = g;
 }
 
@@ -690,7 +717,15 @@ static int class_active(const or_scene* sc, const classes_t* c, const float* eps
 static void groups_of(const or_scene* sc, const float* eps, uint32_t id, const float* uv, gset_t* out) {
     if (id == BG_ID) return;
     if (eps[0] != 0.0f)
-        for (int k = 0; k < 3; ++k) set_add(out, sc->tri[3 * (int64_t)id + k]);
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = sc->tri[3 * (int64_t)id + k];
+            if (sc->n_ctrl > 0) {
+                /* Sec. 6.3: the control vertices the corner combines */
+                for (int32_t j = sc->sub_rowptr[v]; j < sc->sub_rowptr[v + 1]; ++j) set_add(out, sc->sub_cols[j]);
+            } else {
+                set_add(out, v);
+            }
+        }
     classes_t c = texel_classes(sc);
     for (int cls = 0; cls < c.n; ++cls) {
         if (!class_active(sc, &c, eps, cls)) continue;
@@ -715,7 +750,7 @@ static void groups_of(const or_scene* sc, const float* eps, uint32_t id, const f
  * every texture of the class. */
 static int params_of(const or_scene* sc, int64_t g, int64_t* out) {
     int n = 0;
-    if (g < sc->n_verts) {
+    if (g < n_pos(sc)) {
         for (int c = 0; c < 3; ++c) out[n++] = 3 * g + c;
         return n;
     }
@@ -874,7 +909,7 @@ int or_estimate_full(const or_scene* sc, const float* theta, const or_view* view
             }
             for (int64_t g = 0; g < G; ++g) {
                 int active;
-                if (g < sc->n_verts) {
+                if (g < n_pos(sc)) {
                     active = eps[0] != 0.0f;
                 } else {
                     active = 0;
@@ -898,7 +933,7 @@ int or_estimate_full(const or_scene* sc, const float* theta, const or_view* view
 /* ------------------------------------------------------------------ */
 
 static int64_t group_of_param(const or_scene* sc, int64_t i) {
-    if (i < 3 * (int64_t)sc->n_verts) return i / 3;
+    if (i < 3 * n_pos(sc)) return i / 3;
     int t = block_of(sc, i) - 1;
     classes_t c = texel_classes(sc);
     int64_t texel = (i - tex_offset(sc, t)) / sc->tex_c[t];

@@ -41,6 +41,14 @@ typedef struct {
                                /* nearest `layers` fragments of a pixel are   */
                                /* composited front to back, alpha = channel 3 */
                                /* of the albedo (which then has 4 channels)   */
+    /* Subdivision surface (Sec. 6.3): when n_ctrl > 0 the position        */
+    /* parameters are n_ctrl control vertices and the n_verts vertices of  */
+    /* tri are the tessellated surface, vertex j = sum over k in           */
+    /* [rowptr[j], rowptr[j+1]) of w[k] * control vertex cols[k].          */
+    int32_t n_ctrl;
+    const int32_t* sub_rowptr;
+    const int32_t* sub_cols;
+    const float* sub_w;
 } or_scene;
 
 typedef struct {

@@ -25,7 +25,9 @@ class Scene(C.Structure):
                 ("tex_c", C.c_int32 * MAX_TEX),
                 ("shading", C.c_int32), ("tex_mode", C.c_int32),
                 ("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3),
-                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32)]
+                ("ambient", C.c_float), ("diffuse", C.c_float), ("layers", C.c_int32),
+                ("n_ctrl", C.c_int32), ("sub_rowptr", C.c_void_p), ("sub_cols", C.c_void_p),
+                ("sub_w", C.c_void_p)]
 
 
 class View(C.Structure):
@@ -85,6 +87,9 @@ SIGNATURES = {
                                         C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
     "dr_estimate_grad_image": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
                                          C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
+    "dr_subdivide_sizes": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "dr_subdivide": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "dr_decode_grad": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_float), C.c_int32, C.c_int32, _vp]),
     "dr_step": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, _vp, _vp, C.POINTER(C.c_float), C.c_int32,
                           C.POINTER(Optim)]),

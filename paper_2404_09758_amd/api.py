@@ -67,6 +67,29 @@ def make_optim(kind, averaging, lr, beta1=0.9, beta2=0.999, eps_hat=1e-8) -> L.O
     return o
 
 
+def subdivide(tri, corner_uv, n_verts, levels):
+    """Catmull-Clark tessellation of a triangle control mesh by the library
+    (dr_subdivide, host): dict(tri, corner_uv, n_fine, rowptr, cols, w)."""
+    lib = L.load()
+    tri = np.ascontiguousarray(tri, np.int32)
+    cuv = np.ascontiguousarray(corner_uv, np.float32)
+    nv, nt, nnz = C.c_int32(), C.c_int32(), C.c_int64()
+    st = lib.dr_subdivide_sizes(tri.ctypes.data, int(n_verts), int(tri.shape[0]), int(levels), C.byref(nv),
+                                C.byref(nt), C.byref(nnz))
+    if st != 0:
+        raise DRError(f"dr_subdivide_sizes failed: {L.STATUS.get(st, st)}")
+    out = {"tri": np.zeros((nt.value, 3), np.int32), "corner_uv": np.zeros((nt.value, 3, 2), np.float32),
+           "rowptr": np.zeros(nv.value + 1, np.int32), "cols": np.zeros(max(nnz.value, 1), np.int32),
+           "w": np.zeros(max(nnz.value, 1), np.float32), "n_fine": nv.value}
+    st = lib.dr_subdivide(tri.ctypes.data, cuv.ctypes.data, int(n_verts), int(tri.shape[0]), int(levels),
+                          out["tri"].ctypes.data, out["corner_uv"].ctypes.data, out["rowptr"].ctypes.data,
+                          out["cols"].ctypes.data, out["w"].ctypes.data)
+    if st != 0:
+        raise DRError(f"dr_subdivide failed: {L.STATUS.get(st, st)}")
+    out["cols"], out["w"] = out["cols"][: nnz.value], out["w"][: nnz.value]
+    return out
+
+
 class Context:
     """A scene bound to one GPU: topology, UVs, texture shapes and shading.
 
@@ -79,14 +102,24 @@ class Context:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
             raise ValueError("the estimator runs on a GPU device")
+        levels = int(getattr(scene, "subdiv_levels", 0))
         with torch.cuda.device(self.device):
-            self.tri = torch.as_tensor(np.ascontiguousarray(scene.tri, np.int32), device=self.device)
-            self.corner_uv = torch.as_tensor(np.ascontiguousarray(scene.corner_uv, np.float32),
-                                             device=self.device)
+            tri, cuv, n_verts = scene.tri, scene.corner_uv, int(scene.pos.shape[0])
+            self.surface = None
+            if levels > 0:
+                # scene.tri / corner_uv are the control mesh: tessellate it
+                self.surface = subdivide(scene.tri, scene.corner_uv, n_verts, levels)
+                tri, cuv = self.surface["tri"], self.surface["corner_uv"]
+            self.tri = torch.as_tensor(np.ascontiguousarray(tri, np.int32), device=self.device)
+            self.corner_uv = torch.as_tensor(np.ascontiguousarray(cuv, np.float32), device=self.device)
             shapes = [tuple(t.shape) for t in scene.tex]
             s = L.Scene()
-            s.n_verts = int(scene.pos.shape[0])
+            s.n_verts = n_verts if levels == 0 else int(self.surface["n_fine"])
             s.n_tris = int(self.tri.shape[0])
+            if levels > 0:
+                self.sub = [torch.as_tensor(self.surface[k], device=self.device) for k in ("rowptr", "cols", "w")]
+                s.n_ctrl = n_verts
+                s.sub_rowptr, s.sub_cols, s.sub_w = (t.data_ptr() for t in self.sub)
             s.tri = self.tri.data_ptr()
             s.corner_uv = self.corner_uv.data_ptr()
             s.n_tex = len(shapes)

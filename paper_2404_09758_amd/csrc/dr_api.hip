@@ -112,6 +112,10 @@ struct dr_ctx {
     double* partials = nullptr;
     long long partial_slots = 0;
     unsigned long long* stats = nullptr;
+    int* tri_rowptr = nullptr;      // subdivision surface: control vertices per triangle
+    int* tri_cols = nullptr;
+    float* fpos = nullptr;          // tessellated positions per (pair, sign)
+    long long fpos_slots = 0;
     Timer timer;
 };
 
@@ -223,6 +227,65 @@ static dr_status check_tuning(dr_ctx* c, const dr_tuning* t) {
 
 // ------------------------------------------------------------- create --
 
+// Subdivision surface: check the tessellation map and build, per
+// tessellated triangle, the ascending list of control vertices its three
+// corners combine (the vertex groups a pixel on it credits).
+static dr_status setup_subdivision(dr_ctx* c, const dr_scene* s) {
+    const long long nv = s->n_verts, nt = s->n_tris;
+    std::vector<int> rowptr((size_t)nv + 1), tri((size_t)(3 * nt));
+    HIPCHK(c, hipMemcpy(rowptr.data(), s->sub_rowptr, rowptr.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (rowptr[0] != 0) return fail(c, DR_E_INVALID, "sub_rowptr[0] must be 0");
+    for (long long j = 0; j < nv; ++j)
+        if (rowptr[j + 1] < rowptr[j]) return fail(c, DR_E_INVALID, "sub_rowptr must not decrease");
+    const long long nnz = rowptr[nv];
+    std::vector<int> cols((size_t)(nnz > 0 ? nnz : 1));
+    if (nnz > 0) HIPCHK(c, hipMemcpy(cols.data(), s->sub_cols, (size_t)nnz * sizeof(int), hipMemcpyDeviceToHost));
+    for (long long k = 0; k < nnz; ++k)
+        if (cols[k] < 0 || cols[k] >= s->n_ctrl) return fail(c, DR_E_INVALID, "sub_cols out of range");
+    for (long long j = 0; j < nv; ++j)
+        for (long long k = rowptr[j] + 1; k < rowptr[j + 1]; ++k)
+            if (cols[k] <= cols[k - 1]) return fail(c, DR_E_INVALID, "sub_cols must ascend within a row");
+    HIPCHK(c, hipMemcpy(tri.data(), s->tri, tri.size() * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<int> trp(1, 0), tcols;
+    std::vector<int> u;
+    for (long long t = 0; t < nt; ++t) {
+        u.clear();
+        for (int k = 0; k < 3; ++k) {
+            int v = tri[(size_t)(3 * t + k)];
+            u.insert(u.end(), cols.begin() + rowptr[v], cols.begin() + rowptr[v + 1]);
+        }
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        tcols.insert(tcols.end(), u.begin(), u.end());
+        if (tcols.size() >= (size_t)0x7FFFFFFF) return fail(c, DR_E_UNSUPPORTED, "tessellation map too large");
+        trp.push_back((int)tcols.size());
+    }
+    if (tcols.empty()) tcols.push_back(0);
+    HIPCHK(c, hipMalloc(&c->tri_rowptr, trp.size() * sizeof(int)));
+    HIPCHK(c, hipMalloc(&c->tri_cols, tcols.size() * sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->tri_rowptr, trp.data(), trp.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->tri_cols, tcols.data(), tcols.size() * sizeof(int), hipMemcpyHostToDevice));
+    c->sc.tri_rowptr = c->tri_rowptr;
+    c->sc.tri_cols = c->tri_cols;
+    return DR_OK;
+}
+
+// Subdivision surface: tessellate theta (perturbed as dp says) for
+// n_pairs x nsign (pair, sign) slots into c->fpos; *out = null otherwise.
+static dr_status tessellate(dr_ctx* c, const float* theta, const DPert& dp, int n_pairs, int nsign, float sgn0,
+                            float sgn1, const float** out) {
+    *out = nullptr;
+    if (c->sc.n_ctrl == 0) return DR_OK;
+    dr_status s = grow(c, &c->fpos, &c->fpos_slots, (long long)n_pairs * nsign,
+                       (size_t)c->sc.n_verts * 3 * sizeof(float), false);
+    if (s) return s;
+    HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] {
+        return launch_subdiv(c->stream, c->sc, dp, theta, n_pairs, nsign, sgn0, sgn1, c->fpos);
+    }));
+    *out = c->fpos;
+    return DR_OK;
+}
+
 extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning* tune, void* stream) {
     if (!out || !s) return DR_E_INVALID;
     *out = nullptr;
@@ -234,7 +297,11 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     if (s->shading != DR_UNLIT && s->n_tex < 1) return DR_E_INVALID;
     if (s->layers < 0 || s->layers > DR_MAX_LAYERS) return DR_E_INVALID;
     if (s->layers > 0 && s->n_tex < 1) return DR_E_INVALID;
-    long long d = 3ll * s->n_verts;
+    if (s->n_ctrl < 0) return DR_E_INVALID;
+    if (s->n_ctrl > 0 && (!s->sub_rowptr || !s->sub_cols || !s->sub_w)) return DR_E_INVALID;
+    if (s->n_ctrl > 0 && s->layers > 0) return DR_E_UNSUPPORTED;
+    const long long n_vg = s->n_ctrl > 0 ? s->n_ctrl : s->n_verts;     // position groups
+    long long d = 3ll * n_vg;
     for (int t = 0; t < s->n_tex; ++t) {
         if (s->tex_w[t] < 1 || s->tex_h[t] < 1 || s->tex_w[t] > 32768 || s->tex_h[t] > 32768) return DR_E_INVALID;
         int want = (t == 2) ? 1 : (t == 0 && s->layers > 0 ? 4 : 3);
@@ -243,7 +310,7 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     }
     if (d >= (1ll << 36)) return DR_E_INVALID;
     // group indices are 32-bit keys in the tile-local aggregation tables
-    long long groups = s->n_verts;
+    long long groups = n_vg;
     for (int t = 0; t < s->n_tex; ++t) groups += (long long)s->tex_w[t] * s->tex_h[t];
     if (groups >= 0xFFFFFFFFll) return DR_E_UNSUPPORTED;
     dr_ctx* c = new (std::nothrow) dr_ctx();
@@ -267,8 +334,15 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
     sc.tri = s->tri;
     sc.cuv = s->corner_uv;
     sc.n_tex = s->n_tex;
-    long long off = 3ll * s->n_verts;
-    long long goff = s->n_verts;
+    sc.n_vg = (int)n_vg;
+    sc.n_ctrl = s->n_ctrl;
+    sc.sub_rowptr = s->sub_rowptr;
+    sc.sub_cols = s->sub_cols;
+    sc.sub_w = s->sub_w;
+    sc.tri_rowptr = nullptr;
+    sc.tri_cols = nullptr;
+    long long off = 3ll * n_vg;
+    long long goff = n_vg;
     sc.n_cls = 0;
     for (int t = 0; t < DRD_MAX_TEX; ++t) {
         sc.tex_w[t] = sc.tex_h[t] = sc.tex_c[t] = 0;
@@ -327,6 +401,17 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
         delete c;
         return ok ? DR_E_INVALID : DR_E_HIP;
     }
+    if (s->n_ctrl > 0) {
+        dr_status st = setup_subdivision(c, s);
+        if (st) {
+            (void)hipGetLastError();
+            if (c->tri_rowptr) (void)hipFree(c->tri_rowptr);
+            if (c->tri_cols) (void)hipFree(c->tri_cols);
+            (void)hipFree(c->stats);
+            delete c;
+            return st;
+        }
+    }
     *out = c;
     return DR_OK;
 }
@@ -335,7 +420,7 @@ extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->recR, c->recS, c->recF, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
-                    c->qtot};
+                    c->qtot, c->tri_rowptr, c->tri_cols, c->fpos};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->timer.destroy();
@@ -443,6 +528,8 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
+    s = tessellate(c, theta, dp, 1, 1, sg, sg, &sa.fpos);
+    if (s) return s;
     HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, 1); }));
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
@@ -565,6 +652,8 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
             ta.act_cls[c->sc.tex_cls[t]] = 1;
             ta.any_act = 1;
         }
+    s = tessellate(c, theta, dp, n_pairs, 2, 1.0f, -1.0f, &sa.fpos);
+    if (s) return s;
     if (full) HIPCHK(c, launch_zero64(c->stream, c->qtot, n_pairs));
     for (long long i0 = 0; i0 < items; i0 += per) {
         int n = (int)std::min(per, items - i0);
@@ -654,6 +743,8 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
+    s = tessellate(c, theta, dp, 1, 1, 1.0f, 1.0f, &sa.fpos);
+    if (s) return s;
     HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n_views); }));
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
@@ -886,6 +977,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
         if (!s.ctx || !s.views || !s.targets || !s.theta || !s.Q || !s.K) return DR_E_INVALID;
         if (s.ctx->device != dev) return DR_E_INVALID;
         if (s.ctx->sc.layers > 0) return DR_E_UNSUPPORTED;     // the batch raster is opaque only
+        if (s.ctx->sc.n_ctrl > 0) return DR_E_UNSUPPORTED;     // and has no tessellation step
         if (opt->kind == DR_ADAM && (!s.m || !s.v)) return DR_E_INVALID;
         if (s.n_views < 1 || s.n_views > DR_MAX_VIEWS) return DR_E_INVALID;
         if (s.bin_capacity < 0 || s.bin_capacity > (1 << 20)) return DR_E_INVALID;

@@ -33,6 +33,17 @@ struct DScene {
     long long cls_goff[DRD_MAX_TEX];     // first group of each class
     int shading, tex_mode;
     int layers;                          // 0 opaque; 1..4 composited fragments
+    // subdivision surface: n_ctrl > 0 control vertices are the position
+    // parameters; tessellated vertex j = sum_k sub_w[k] ctrl[sub_cols[k]],
+    // and tessellated triangle t credits the control vertices
+    // tri_cols[tri_rowptr[t] .. tri_rowptr[t+1]) (the union of its corners')
+    int n_vg;                            // position groups: n_ctrl, else n_verts
+    int n_ctrl;
+    const int* sub_rowptr;
+    const int* sub_cols;
+    const float* sub_w;
+    const int* tri_rowptr;
+    const int* tri_cols;
     float light[3], light_rgb[3], ambient, diffuse;
     long long d, G;
     int words;                           // ceil(d / 32) sign words per pair

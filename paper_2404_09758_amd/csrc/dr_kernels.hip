@@ -49,11 +49,14 @@ __global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, 
 
 // Triangle t of one (item, sign): perturbed vertices, projection, snap,
 // setup record, and its entries in the bins of the tiles it may cover.
+// fpos: the perturbed tessellated vertex positions of this (pair, sign) of a
+// subdivision surface, or null (positions are the perturbed parameters).
 __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
                                           const uint32_t* __restrict__ pb, float e0, float sgn, int t,
                                           TriR* __restrict__ recR, TriS* __restrict__ recS,
                                           TriF* __restrict__ recF, unsigned* __restrict__ counts,
-                                          unsigned* __restrict__ bins, int tile_px, int cap) {
+                                          unsigned* __restrict__ bins, int tile_px, int cap,
+                                          const float* __restrict__ fpos) {
     int vid[3];
     float p[9];
     Vtx v[3];
@@ -61,9 +64,15 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     for (int k = 0; k < 3; ++k) {
         vid[k] = sc.tri[3 * (long long)t + k];
         long long base = 3 * (long long)vid[k];
-        p[3 * k + 0] = pval(theta, base + 0, e0, pb, sgn);
-        p[3 * k + 1] = pval(theta, base + 1, e0, pb, sgn);
-        p[3 * k + 2] = pval(theta, base + 2, e0, pb, sgn);
+        if (fpos) {
+            p[3 * k + 0] = fpos[base + 0];
+            p[3 * k + 1] = fpos[base + 1];
+            p[3 * k + 2] = fpos[base + 2];
+        } else {
+            p[3 * k + 0] = pval(theta, base + 0, e0, pb, sgn);
+            p[3 * k + 1] = pval(theta, base + 1, e0, pb, sgn);
+            p[3 * k + 2] = pval(theta, base + 2, e0, pb, sgn);
+        }
         v[k] = xform(vw, p[3 * k + 0], p[3 * k + 1], p[3 * k + 2]);
     }
     TriR r;
@@ -148,10 +157,37 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     int item = a.item0 + li;
     int pair = item / a.n_views, view = item % a.n_views;
     const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
+    const float* fpos = a.fpos ? a.fpos + ((long long)pair * a.nsign + s) * 3 * sc.n_verts : nullptr;
     setup_tri(sc, a.views.v[view], a.theta, pb, a.pert.eps[0], a.sgn[s], t, a.recR + (long long)slot * sc.n_tris,
               a.recS + (long long)slot * sc.n_tris, a.recF + (long long)slot * sc.n_tris,
               a.counts + (long long)slot * a.max_tiles, a.bins + (long long)slot * a.max_tiles * a.cap, a.tile,
-              a.cap);
+              a.cap, fpos);
+}
+
+// Tessellated vertex positions of a subdivision surface for every (pair,
+// sign) of a call: vertex j, coordinate c = the row's weights times the
+// perturbed control coordinates, added in row order from zero.
+__global__ void __launch_bounds__(256) k_subdiv(DScene sc, DPert pert, const float* __restrict__ theta, int nsign,
+                                                float sgn0, float sgn1, float* __restrict__ fpos) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sc.n_verts) return;
+    int slot = blockIdx.y;                       // (pair, sign)
+    int pair = slot / nsign, s = slot % nsign;
+    const uint32_t* pb = pert.bits ? pert.bits + (long long)pair * sc.words : nullptr;
+    float sgn = s == 0 ? sgn0 : sgn1;
+    float e0 = pert.eps[0];
+    int k0 = sc.sub_rowptr[j], k1 = sc.sub_rowptr[j + 1];
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = k0; k < k1; ++k) {
+        float w = sc.sub_w[k];
+        long long base = 3 * (long long)sc.sub_cols[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = acc[c] + w * pval(theta, base + c, e0, pb, sgn);
+    }
+    float* out = fpos + ((long long)slot * sc.n_verts + j) * 3;
+    out[0] = acc[0];
+    out[1] = acc[1];
+    out[2] = acc[2];
 }
 
 // ----------------------------------------------------------------- tile --
@@ -311,6 +347,52 @@ __device__ __forceinline__ void wave_vertices(GroupTable<LOG2T>& tb, long long* 
         }
         if (mine) active = false;
         pending &= ~m;
+    }
+}
+
+// Subdivision surface: the same per-wave combine for pixels whose + and -
+// renders show the same tessellated triangle, crediting the control
+// vertices of the triangle's list; the wave's lanes share the list.  Must
+// be called by every lane of the wave.
+template <int LOG2T>
+__device__ __forceinline__ void wave_ctrl(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
+                                          unsigned* __restrict__ K, const DScene& sc, bool active, unsigned tri,
+                                          long long q) {
+    int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        int leader = __ffsll((unsigned long long)pending) - 1;
+        unsigned lt = __builtin_amdgcn_readfirstlane(__shfl(tri, leader));
+        bool mine = active && tri == lt;
+        unsigned long long m = __ballot(mine);
+        long long v = mine ? q : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        unsigned c = (unsigned)__popcll(m);
+        int b0 = sc.tri_rowptr[lt], b1 = sc.tri_rowptr[lt + 1];
+        for (int j = b0 + lane; j < b1; j += 64) table_add<LOG2T>(tb, Rp, K, (unsigned)sc.tri_cols[j], v, c);
+        if (mine) active = false;
+        pending &= ~m;
+    }
+}
+
+// The union of two tessellated triangles' control vertices (both lists
+// ascending), each once, for one pixel.
+template <int LOG2T>
+__device__ __forceinline__ void ctrl_union_add(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
+                                               unsigned* __restrict__ K, const DScene& sc, unsigned t0,
+                                               unsigned t1, long long q) {
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (t0 != DRD_BG) { a0 = sc.tri_rowptr[t0]; a1 = sc.tri_rowptr[t0 + 1]; }
+    if (t1 != DRD_BG) { b0 = sc.tri_rowptr[t1]; b1 = sc.tri_rowptr[t1 + 1]; }
+    int i = a0, j = b0;
+    while (i < a1 || j < b1) {
+        int ga = i < a1 ? sc.tri_cols[i] : 0x7FFFFFFF;
+        int gb = j < b1 ? sc.tri_cols[j] : 0x7FFFFFFF;
+        int g = ga < gb ? ga : gb;
+        if (ga == g) ++i;
+        if (gb == g) ++j;
+        table_add<LOG2T>(tb, Rp, K, (unsigned)g, q, 1u);
     }
 }
 
@@ -485,7 +567,11 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 q = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
                 if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
-            if (J.act_pos) {
+            if (J.act_pos && sc.n_ctrl > 0) {
+                bool same = act && id[0] == id[1];
+                wave_ctrl<LOG2T>(S.table, J.Rp, J.K, sc, same, id[0], q);
+                if (act && !same) ctrl_union_add<LOG2T>(S.table, J.Rp, J.K, sc, id[0], id[1], q);
+            } else if (J.act_pos) {
                 // same triangle in both renders: combined per wave
                 bool same = act && id[0] == id[1];
                 wave_vertices<LOG2T>(S.table, J.Rp, J.K, same, id[0], vids[0][0], vids[0][1], vids[0][2], q);
@@ -908,7 +994,7 @@ __global__ void __launch_bounds__(256) k_sum_tiles(const double* __restrict__ pa
 // every texture of its class.  Calls fn(param index, block).
 template <typename Fn>
 __device__ __forceinline__ void for_params(const DScene& sc, long long g, Fn fn) {
-    if (g < sc.n_verts) {
+    if (g < sc.n_vg) {
         fn(3 * g + 0, 0);
         fn(3 * g + 1, 0);
         fn(3 * g + 2, 0);
@@ -949,7 +1035,7 @@ __global__ void __launch_bounds__(256) k_broadcast(FoldArgs a) {
     const DScene& sc = a.sc;
     if (g >= sc.G) return;
     bool active = false;
-    if (g < sc.n_verts) {
+    if (g < sc.n_vg) {
         active = a.eps[0] != 0.0f;
     } else {
         for (int c = 0; c < sc.n_cls; ++c) {
@@ -1099,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
     setup_tri(sc, vw, S.theta, S.bits + (long long)I.pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t,
               b.recR + I.rec_off + (long long)s * sc.n_tris, b.recS + I.rec_off + (long long)s * sc.n_tris,
               b.recF + I.rec_off + (long long)s * sc.n_tris, b.counts + I.cnt_off + (long long)s * tiles,
-              b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap);
+              b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap, nullptr);
 }
 
 // Raster / shade / scatter of every (scene, pair, view, tile) unit in one
@@ -1222,6 +1308,13 @@ hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, in
     if (tile == 8) launch_tile_t<8>(st, a, mode, grid);
     else if (tile == 16) launch_tile_t<16>(st, a, mode, grid);
     else launch_tile_t<32>(st, a, mode, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_subdiv(hipStream_t st, const DScene& sc, const DPert& pert, const float* theta, int n_pairs,
+                         int nsign, float sgn0, float sgn1, float* fpos) {
+    dim3 grid((unsigned)((sc.n_verts + 255) / 256), (unsigned)(n_pairs * nsign));
+    hipLaunchKernelGGL(k_subdiv, grid, dim3(256), 0, st, sc, pert, theta, nsign, sgn0, sgn1, fpos);
     return hipGetLastError();
 }
 

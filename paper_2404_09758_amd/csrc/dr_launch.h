@@ -31,6 +31,7 @@ struct SetupArgs {
     TriF* recF;
     unsigned* counts;
     unsigned* bins;
+    const float* fpos;      // subdivision surface: [pairs, nsign, n_verts, 3] positions, else null
 };
 
 struct TileArgs {
@@ -166,6 +167,8 @@ struct BatchArgs {
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
                         long long d, int words, int n_pairs, uint32_t* bits);
 hipError_t launch_setup(hipStream_t st, const SetupArgs& a, int n_items);
+hipError_t launch_subdiv(hipStream_t st, const DScene& sc, const DPert& pert, const float* theta, int n_pairs,
+                         int nsign, float sgn0, float sgn1, float* fpos);
 hipError_t launch_tile(hipStream_t st, const TileArgs& a, int tile, int mode, int n_items, int max_tiles);
 hipError_t launch_sum_tiles(hipStream_t st, const double* partials, int max_tiles, const DViews& views,
                             int n_views, double* out);

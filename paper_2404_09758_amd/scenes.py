@@ -294,6 +294,7 @@ class Scene:
     steps: int = 1
     seed: int = 0
     layers: int = 0                 # 0 opaque; 1..4 semi-transparent (albedo RGBA)
+    subdiv_levels: int = 0          # > 0: tri / corner_uv / pos are a Catmull-Clark control mesh
 
     @property
     def n_verts(self):
@@ -404,6 +405,40 @@ def make_layered(layers: int, seed=9, res=512, views=4, pairs=8) -> Scene:
     return Scene(f"layered{layers}", f.astype(np.int32), uv, v.astype(np.float32), [tex0], tgt_pos, [tgt], vs,
                  shading=SHADING_LAMBERT, eps=[eps_pos, 1.0 / 255.0], lr=[eps_pos, 1.0 / 255.0],
                  n_pairs=pairs, optimizer=OPT_ADAM, steps=1, seed=seed, layers=layers)
+
+
+def make_subdiv(seed=4, res=1024, tex_res=1024, views=4, pairs=8, control_freq=10, levels=2,
+                 shading=SHADING_GGX) -> Scene:
+    """Subdivision-surface variant of the paper workload (Sec. 6.3 and the
+    teaser: a 2K-triangle control mesh, two Catmull-Clark levels, about 50K
+    triangles): the control mesh is a frequency-10 geodesic icosphere (2000
+    triangles, 1002 vertices) whose vertices are the position parameters;
+    two levels give 24 000 quads = 48 000 tessellated triangles.  Albedo,
+    normal and roughness maps at 1024^2, GGX, 4 views, 8 pairs, Adam with
+    lr = eps.  The target displaces the control vertices radially."""
+    v, f, uv = _sphere_scene(control_freq)
+    t = tex_res
+    if shading == SHADING_GGX:
+        tex = [np.full((t, t, 3), 0.5, np.float32), np.empty((t, t, 3), np.float32),
+               np.full((t, t, 1), 0.5, np.float32)]
+        tex[1][:] = (0.5, 0.5, 1.0)
+        hgt = value_noise_2d(t, t, seed * 1000 + 32, channels=1, f0=8)
+        tgt = [value_noise_2d(t, t, seed * 1000 + 31, channels=3).astype(np.float32),
+               normal_map_from_height(hgt).astype(np.float32),
+               (0.2 + 0.6 * value_noise_2d(t, t, seed * 1000 + 33, channels=1)).astype(np.float32)]
+    else:
+        tex = [np.full((t, t, 3), 0.5, np.float32)]
+        tgt = [value_noise_2d(t, t, seed * 1000 + 31, channels=3).astype(np.float32)]
+    tgt_pos = _radial_displace(v, seed * 1000 + 34).astype(np.float32)
+    fy = 1.0 / math.tan(math.radians(FOVY_DEG) / 2)
+    eps_pos = 1.5 * (CAM_DIST / fy) * 2.0 / res
+    q = 1.0 / 255.0
+    eps = [eps_pos] + [q] * len(tex)
+    vs = [look_at_view(res, res, 90.0 * k, 20.0) for k in range(views)]
+    return Scene("subdiv", f.astype(np.int32), uv, v.astype(np.float32), tex, tgt_pos, tgt, vs,
+                 shading=shading, light_rgb=np.full(3, 3.0 if shading == SHADING_GGX else 1.0, np.float32),
+                 ambient=0.03 if shading == SHADING_GGX else 0.1, eps=eps, lr=list(eps), n_pairs=pairs,
+                 optimizer=OPT_ADAM, steps=1, seed=seed, subdiv_levels=levels)
 
 
 def make_paper(seed=3, res=1024, tex_res=1024, views=4, pairs=8, control_freq=12, splits=2) -> Scene:

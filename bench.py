@@ -76,7 +76,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "mid", "tiny", "batch64", "soup", "layers"])
+    ap.add_argument("--config", default="paper",
+                    choices=["paper", "mid", "tiny", "batch64", "soup", "layers", "subdiv"])
     ap.add_argument("--soup-steps", type=int, default=100, help="Adam steps per run of the soup config")
     ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
     ap.add_argument("--no-cpu", action="store_true")
@@ -257,6 +258,8 @@ def main():
     results = {}
     modes = {"batched": (tile, cap, 0), "plain": (tile, cap, 1)}
     order = ["graph", "batched", "plain"] if args.mode == "both" else [args.mode]
+    if sc.subdiv_levels > 0:
+        order = [m for m in order if m != "graph"] or ["batched"]     # the batch form is mesh-only
     for name in order:
         if name == "graph":
             results[name] = run_graph_mode([sc], [tg], args.steps, args.warmup, api, batch, torch, dev, tile=tile,
@@ -291,7 +294,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {sc.views[0].width}x{sc.views[0].height} px, "
-                               f"{sc.n_tris} tris, {len(sc.views)} views x {sc.n_pairs} pairs, "
+                               f"{ctx.tri.shape[0]} tris"
+                               + (f" (Catmull-Clark x{sc.subdiv_levels} of {sc.n_tris})" if sc.subdiv_levels else "")
+                               + f", {len(sc.views)} views x {sc.n_pairs} pairs, "
                                f"d={sc.n_params}, {['unlit', 'lambert', 'ggx'][sc.shading]}",
                    "mode": main_mode, "tile_px": tile, "bin_capacity": cap,
                    "pixel_estimates_per_step": px_per_step},

@@ -528,6 +528,7 @@ CONFIGS = {
     "paper": make_paper,
     "octa": make_octa_small,
     "diff": make_diff_run,
+    "subdiv": make_subdiv,
 }
 
 

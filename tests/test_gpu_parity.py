@@ -405,3 +405,100 @@ def test_layered_scene_argument_checks():
     bad.layers = 2                                          # opacity needs an RGBA albedo
     with pytest.raises(api.DRError):
         api.Context(bad, DEV)
+
+
+# ------------------------------------------------- subdivision surfaces --
+
+def subdiv_scene(name):
+    """Catmull-Clark surfaces over icosphere control meshes, several tiles."""
+    if name == "cc_unlit":
+        sc = H.sphere_scene(1, 0, res=(96, 80), shading=S.SHADING_UNLIT, tex_shapes=((32, 32, 3),), seed=7,
+                            views=2)
+    elif name == "cc_ggx":
+        sc = H.sphere_scene(2, 0, res=(72, 88), shading=S.SHADING_GGX,
+                            tex_shapes=((32, 32, 3), (32, 32, 3), (16, 16, 1)), seed=8, views=1)
+    elif name == "cc_lambert1":
+        sc = H.sphere_scene(3, 0, res=(64, 64), shading=S.SHADING_LAMBERT, tex_shapes=((24, 24, 3),), seed=9,
+                            views=2)
+    else:
+        raise KeyError(name)
+    sc.subdiv_levels = 1 if name.endswith("1") else 2
+    return sc
+
+
+@pytest.mark.parametrize("name", ["cc_unlit", "cc_ggx", "cc_lambert1"])
+@pytest.mark.parametrize("tile,cap", [(8, 256), (16, 256), (32, 1)])
+def test_subdiv_render_bit_exact(name, tile, cap):
+    sc = subdiv_scene(name)
+    o = oracle.Oracle(sc)
+    ctx = api.Context(sc, DEV, tuning=(tile, cap, 1))
+    assert np.array_equal(ctx.surface["tri"], o.surface["tri"])
+    theta = sc.flat_params()
+    for v in sc.views:
+        rgb_o, id_o, uv_o = o.render(theta, v)
+        rgb, ids, uv = ctx.render(dev(theta), v)
+        assert np.array_equal(host(ids).view(np.uint32), id_o)
+        assert np.array_equal(host(uv), uv_o)
+        assert np.array_equal(host(rgb), rgb_o)
+    # a perturbed render: the tessellation of theta + s eps
+    pert = {"seed": 3, "step": 2, "pair": 1, "sign": -1, "eps": sc.eps}
+    s = oracle.signs(3, 2, 1, 0, o.d)
+    rgb_o, id_o, _ = o.render(theta, sc.views[0], signs_=s, sign=-1, eps=sc.eps)
+    rgb, ids, _ = ctx.render(dev(theta), sc.views[0], pert=pert)
+    assert np.array_equal(host(ids).view(np.uint32), id_o)
+    assert np.array_equal(host(rgb), rgb_o)
+
+
+@pytest.mark.parametrize("name,pairs,tuning,form", [("cc_unlit", 3, (16, 256, 0), "loss"),
+                                                    ("cc_ggx", 2, (8, 4, 1), "loss"),
+                                                    ("cc_lambert1", 2, (32, 256, 0), "loss"),
+                                                    ("cc_unlit", 2, (16, 256, 1), "image"),
+                                                    ("cc_ggx", 1, (16, 256, 0), "full")])
+def test_subdiv_estimate_bit_exact(name, pairs, tuning, form):
+    sc = subdiv_scene(name)
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    if form == "image":
+        rng = np.random.default_rng(5)
+        tg = [rng.standard_normal((int(v.height), int(v.width), 3)).astype(np.float32) for v in sc.views]
+    else:
+        tg = targets_of(o, sc)
+    kw = {"image_grad": form == "image", "full_image": form == "full"}
+    Qo, Ko, _, st = o.estimate(theta, sc.views, tg, 11, 4, pairs, sc.eps, **kw)
+    ctx = api.Context(sc, DEV, tuning=tuning)
+    assert ctx.d == o.d and ctx.G == o.G
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 11, 4, pairs, sc.eps, **kw)
+    Qg, Kg = host(Q), host(K).view(np.uint32)
+    assert np.array_equal(Kg, Ko), f"K differs at {np.nonzero(Kg != Ko)[0][:10]}"
+    assert np.array_equal(Qg, Qo), f"Q differs at {np.nonzero(Qg != Qo)[0][:10]}"
+    nv = 3 * sc.pos.shape[0]
+    assert np.count_nonzero(Qo[:nv]) > 0.5 * nv          # control vertices receive the estimate
+    gs = ctx.stats()
+    assert gs["saturations"] == st["saturations"] and gs["nonfinite"] == st["nonfinite"]
+
+
+def test_subdiv_step_and_loss_match_oracle():
+    sc = subdiv_scene("cc_unlit")
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    loss = host(ctx.loss(dev(theta), sc.views, [dev(t) for t in tg]))
+    ref = [o.pixel_loss(theta, v, t).astype(np.float64).sum() for v, t in zip(sc.views, tg)]
+    assert np.allclose(loss, ref, rtol=1e-12)
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 2, 1, 2, sc.eps)
+    th_o, m_o, v_o = theta.copy(), np.zeros(o.d, np.float32), np.zeros(o.d, np.float32)
+    o.step(th_o, m_o, v_o, 1, Qo, Ko, sc.eps, 2, kind=S.OPT_ADAM, averaging=S.AVG_COUNT, lr=sc.eps)
+    th = dev(theta)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    Q, K = ctx.estimate_grad(th, sc.views, [dev(t) for t in tg], 2, 1, 2, sc.eps)
+    ctx.step(th, m, v, 1, Q, K, sc.eps, 2, kind=api.ADAM, averaging=api.AVG_COUNT, lr=sc.eps)
+    assert np.array_equal(host(th), th_o)
+
+
+def test_subdiv_argument_checks():
+    sc = subdiv_scene("cc_unlit")
+    sc.layers = 2
+    sc.tex = [np.zeros((32, 32, 4), np.float32)]
+    with pytest.raises(api.DRError):
+        api.Context(sc, DEV)                                 # layered subdivision surfaces: unsupported

@@ -290,12 +290,27 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
 #define HASH_EMPTY 0xFFFFFFFFu
 #define HASH_PROBES 64
 
+// A slot packs the group's sum and count into one 64-bit word,
+// sum * 2^12 + count, so one LDS atomic adds both: a tile has at most 1024
+// pixels, so the count stays below 2^12, and |sum| <= 1024 * 2^37 keeps the
+// packed word within int64.
+#define PACK_SHIFT 12
+#define PACK_MASK ((1ull << PACK_SHIFT) - 1ull)
+
 template <int LOG2T>
 struct GroupTable {
     unsigned key[1 << LOG2T];
-    unsigned long long sum[1 << LOG2T];
-    unsigned cnt[1 << LOG2T];
+    unsigned long long sum[1 << LOG2T];     // packed sum and count
 };
+
+__device__ __forceinline__ unsigned long long pack_sc(long long q, unsigned c) {
+    return ((unsigned long long)q << PACK_SHIFT) + (unsigned long long)c;
+}
+
+__device__ __forceinline__ void unpack_sc(unsigned long long w, long long& q, unsigned& c) {
+    c = (unsigned)(w & PACK_MASK);
+    q = (long long)(w - c) >> PACK_SHIFT;
+}
 
 __device__ __forceinline__ void global_add(long long* __restrict__ Rp, unsigned* __restrict__ K, long long g,
                                            long long q, unsigned c) {
@@ -312,8 +327,7 @@ __device__ __forceinline__ void table_add(GroupTable<LOG2T>& tb, long long* __re
         unsigned k = __hip_atomic_load(&tb.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == HASH_EMPTY) k = atomicCAS(&tb.key[h], HASH_EMPTY, g);
         if (k == HASH_EMPTY || k == g) {
-            if (q != 0) atomicAdd(&tb.sum[h], (unsigned long long)q);
-            atomicAdd(&tb.cnt[h], c);
+            atomicAdd(&tb.sum[h], pack_sc(q, c));
             return;
         }
         h = (h + 1u) & MASK;
@@ -469,7 +483,6 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         for (int j = tid; j < TSIZE; j += TB) {
             S.table.key[j] = HASH_EMPTY;
             S.table.sum[j] = 0ull;
-            S.table.cnt[j] = 0u;
         }
     }
     __syncthreads();
@@ -658,7 +671,12 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
             unsigned g = S.table.key[j];
-            if (g != HASH_EMPTY) global_add(J.Rp, J.K, (long long)g, (long long)S.table.sum[j], S.table.cnt[j]);
+            if (g != HASH_EMPTY) {
+                long long q;
+                unsigned c;
+                unpack_sc(S.table.sum[j], q, c);
+                global_add(J.Rp, J.K, (long long)g, q, c);
+            }
         }
     }
 }
@@ -727,7 +745,6 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         for (int j = tid; j < TSIZE; j += TB) {
             S.table.key[j] = HASH_EMPTY;
             S.table.sum[j] = 0ull;
-            S.table.cnt[j] = 0u;
         }
     }
     __syncthreads();
@@ -914,7 +931,12 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
             unsigned g = S.table.key[j];
-            if (g != HASH_EMPTY) global_add(J.Rp, J.K, (long long)g, (long long)S.table.sum[j], S.table.cnt[j]);
+            if (g != HASH_EMPTY) {
+                long long q;
+                unsigned c;
+                unpack_sc(S.table.sum[j], q, c);
+                global_add(J.Rp, J.K, (long long)g, q, c);
+            }
         }
     }
 }

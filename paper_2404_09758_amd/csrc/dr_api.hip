@@ -97,7 +97,6 @@ struct dr_ctx {
     std::string err;
     TriR* recR = nullptr;
     TriS* recS = nullptr;
-    TriF* recF = nullptr;
     long long rec_slots = 0;
     unsigned* counts = nullptr;
     unsigned* bins = nullptr;
@@ -168,9 +167,6 @@ static dr_status ensure_raster(dr_ctx* c, long long slots, int max_tiles) {
     if (s) return s;
     have = c->rec_slots;
     s = grow(c, &c->recS, &have, slots * c->sc.n_tris, sizeof(TriS), false);
-    if (s) return s;
-    have = c->rec_slots;
-    s = grow(c, &c->recF, &have, slots * c->sc.n_tris, sizeof(TriF), false);
     if (s) return s;
     if (slots * c->sc.n_tris > c->rec_slots) c->rec_slots = slots * c->sc.n_tris;
     s = grow(c, &c->counts, &c->tile_slots, slots * (long long)max_tiles, sizeof(unsigned), true);
@@ -419,7 +415,7 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
 extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->recR, c->recS, c->recF, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
+    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
                     c->qtot, c->tri_rowptr, c->tri_cols, c->fpos};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -525,7 +521,6 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
-    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
     s = tessellate(c, theta, dp, 1, 1, sg, sg, &sa.fpos);
@@ -546,7 +541,6 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
-    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
@@ -619,7 +613,6 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
-    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
     TileArgs ta;
@@ -636,7 +629,6 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
-    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
@@ -740,7 +732,6 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     sa.max_tiles = max_tiles;
     sa.recR = c->recR;
     sa.recS = c->recS;
-    sa.recF = c->recF;
     sa.counts = c->counts;
     sa.bins = c->bins;
     s = tessellate(c, theta, dp, 1, 1, 1.0f, 1.0f, &sa.fpos);
@@ -760,7 +751,6 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     ta.max_tiles = max_tiles;
     ta.recR = c->recR;
     ta.recS = c->recS;
-    ta.recF = c->recF;
     ta.counts = c->counts;
     ta.bins = c->bins;
     ta.stats = c->stats;
@@ -1114,7 +1104,6 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     unsigned* dstep = nullptr;
     if ((st = balloc(b, &bits, (size_t)bits_total, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
         (st = balloc(b, &A.recR, (size_t)rec, false)) || (st = balloc(b, &A.recS, (size_t)rec, false)) ||
-        (st = balloc(b, &A.recF, (size_t)rec, false)) ||
         (st = balloc(b, &A.counts, (size_t)cnt, true)) || (st = balloc(b, &A.bins, (size_t)bin, false)) ||
         (st = balloc(b, &dsc, hs.size(), false)) || (st = balloc(b, &dvw, hv.size(), false)) ||
         (st = balloc(b, &dit, hi.size(), false)) || (st = balloc(b, &dbc1, bc1.size(), false)) ||

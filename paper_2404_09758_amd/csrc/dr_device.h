@@ -89,18 +89,18 @@ struct __align__(16) TriS {
     int pad;
 };
 
-// Per-face shading frame (64 B), computed once per triangle by the setup:
-// the unit face normal and (GGX) the tangent frame of the face's UV map.
-struct __align__(16) TriF {
+// Per-face shading frame: the unit face normal and (GGX) the tangent frame
+// of the face's UV map, formed per shaded pixel from the shading record
+// (measured as fast as storing it per triangle, and 64 B per triangle and
+// render less to write).
+struct TriF {
     float nf[3];
     float T[3];
     float B[3];
-    int pad[7];
 };
 
 static_assert(sizeof(TriR) == 64, "TriR layout");
 static_assert(sizeof(TriS) == 64, "TriS layout");
-static_assert(sizeof(TriF) == 64, "TriF layout");
 
 #define TRI_VALID 1u
 #define TRI_SWAPPED 16u

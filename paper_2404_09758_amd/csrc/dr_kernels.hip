@@ -54,7 +54,7 @@ __global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, 
 __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
                                           const uint32_t* __restrict__ pb, float e0, float sgn, int t,
                                           TriR* __restrict__ recR, TriS* __restrict__ recS,
-                                          TriF* __restrict__ recF, unsigned* __restrict__ counts,
+                                          unsigned* __restrict__ counts,
                                           unsigned* __restrict__ bins, int tile_px, int cap,
                                           const float* __restrict__ fpos) {
     int vid[3];
@@ -131,13 +131,6 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     sh.pad = 0;
     recR[t] = r;
     recS[t] = sh;
-    if (sc.shading != 0) {
-        TriF fr;
-        face_frame(sc.shading, p, sc.cuv + 6 * (long long)t, fr);
-#pragma unroll
-        for (int k = 0; k < 7; ++k) fr.pad[k] = 0;
-        recF[t] = fr;
-    }
     if (bx0 > bx1) return;
     int tx0 = bx0 / tile_px, tx1 = bx1 / tile_px, ty0 = by0 / tile_px, ty1 = by1 / tile_px;
     for (int ty = ty0; ty <= ty1; ++ty)
@@ -159,7 +152,7 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     const uint32_t* pb = a.pert.bits ? a.pert.bits + (long long)pair * sc.words : nullptr;
     const float* fpos = a.fpos ? a.fpos + ((long long)pair * a.nsign + s) * 3 * sc.n_verts : nullptr;
     setup_tri(sc, a.views.v[view], a.theta, pb, a.pert.eps[0], a.sgn[s], t, a.recR + (long long)slot * sc.n_tris,
-              a.recS + (long long)slot * sc.n_tris, a.recF + (long long)slot * sc.n_tris,
+              a.recS + (long long)slot * sc.n_tris,
               a.counts + (long long)slot * a.max_tiles, a.bins + (long long)slot * a.max_tiles * a.cap, a.tile,
               a.cap, fpos);
 }
@@ -335,39 +328,11 @@ __device__ __forceinline__ void table_add(GroupTable<LOG2T>& tb, long long* __re
     global_add(Rp, K, g, q, c);      // crowded table: go straight to memory
 }
 
-// Wave-level combine of the vertex contributions of pixels whose + and -
-// renders show the same triangle: lanes with equal triangle ids are summed
-// with a butterfly and one lane adds the three vertices.  Must be called by
+// Subdivision surface: pixels whose + and - renders show the same
+// tessellated triangle are combined per wave -- lanes with equal triangle
+// ids are summed with a butterfly -- and the wave's lanes then share the
+// table adds of that triangle's control-vertex list.  Must be called by
 // every lane of the wave.
-template <int LOG2T>
-__device__ __forceinline__ void wave_vertices(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
-                                              unsigned* __restrict__ K, bool active, unsigned tri,
-                                              int v0, int v1, int v2, long long q) {
-    int lane = threadIdx.x & 63;
-    unsigned long long pending = __ballot(active);
-    while (pending) {
-        int leader = __ffsll((unsigned long long)pending) - 1;
-        unsigned lt = __shfl(tri, leader);
-        bool mine = active && tri == lt;
-        unsigned long long m = __ballot(mine);
-        long long v = mine ? q : 0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == leader) {
-            unsigned c = (unsigned)__popcll(m);
-            table_add<LOG2T>(tb, Rp, K, (unsigned)v0, v, c);
-            table_add<LOG2T>(tb, Rp, K, (unsigned)v1, v, c);
-            table_add<LOG2T>(tb, Rp, K, (unsigned)v2, v, c);
-        }
-        if (mine) active = false;
-        pending &= ~m;
-    }
-}
-
-// Subdivision surface: the same per-wave combine for pixels whose + and -
-// renders show the same tessellated triangle, crediting the control
-// vertices of the triangle's list; the wave's lanes share the list.  Must
-// be called by every lane of the wave.
 template <int LOG2T>
 __device__ __forceinline__ void wave_ctrl(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
                                           unsigned* __restrict__ K, const DScene& sc, bool active, unsigned tri,
@@ -426,7 +391,6 @@ struct TileJob {
     float sgn[2];
     const TriR* recR[2];                 // records of each sign (index = triangle)
     const TriS* recS[2];
-    const TriF* recF[2];
     unsigned* counts[2];                 // bin counters of each sign (index = tile)
     const unsigned* bins[2];             // bin entries of each sign (tile * cap + k)
     int cap;
@@ -539,7 +503,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 TriR r = J.recR[s][id[s]];
                 TriS sh = J.recS[s][id[s]];
                 TriF fr;
-                if (sc.shading != 0) fr = J.recF[s][id[s]];
+                if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id[s], fr);
                 float alpha;
                 shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id[s], px, py, rgb[s], uv[s],
                             foot[s], alpha);
@@ -587,7 +551,10 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             } else if (J.act_pos) {
                 // same triangle in both renders: combined per wave
                 bool same = act && id[0] == id[1];
-                wave_vertices<LOG2T>(S.table, J.Rp, J.K, same, id[0], vids[0][0], vids[0][1], vids[0][2], q);
+                if (same) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)vids[0][k], q, 1u);
+                }
                 if (act && !same) {
                     // the union of the two triangles' vertices, each once
                     if (id[0] != DRD_BG) {
@@ -800,7 +767,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                 TriR r = J.recR[s][id];
                 TriS sh = J.recS[s][id];
                 TriF fr;
-                if (sc.shading != 0) fr = J.recF[s][id];
+                if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id, fr);
                 float c[3], al;
                 Foot f0;
                 shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id, px, py, c, uv, f0, al);
@@ -969,7 +936,6 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
         int slot = li * NS + (s < NS ? s : 0);
         J.recR[s] = a.recR + (long long)slot * sc.n_tris;
         J.recS[s] = a.recS + (long long)slot * sc.n_tris;
-        J.recF[s] = a.recF + (long long)slot * sc.n_tris;
         J.counts[s] = a.counts + (long long)slot * a.max_tiles;
         J.bins[s] = a.bins + (long long)slot * a.max_tiles * a.cap;
     }
@@ -1206,7 +1172,7 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
     int tiles = vw.tiles_x * vw.tiles_y;
     setup_tri(sc, vw, S.theta, S.bits + (long long)I.pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t,
               b.recR + I.rec_off + (long long)s * sc.n_tris, b.recS + I.rec_off + (long long)s * sc.n_tris,
-              b.recF + I.rec_off + (long long)s * sc.n_tris, b.counts + I.cnt_off + (long long)s * tiles,
+              b.counts + I.cnt_off + (long long)s * tiles,
               b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap, nullptr);
 }
 
@@ -1237,7 +1203,6 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE) k_til
     for (int s = 0; s < 2; ++s) {
         J.recR[s] = b.recR + I.rec_off + (long long)s * sc.n_tris;
         J.recS[s] = b.recS + I.rec_off + (long long)s * sc.n_tris;
-        J.recF[s] = b.recF + I.rec_off + (long long)s * sc.n_tris;
         J.counts[s] = b.counts + I.cnt_off + (long long)s * tiles;
         J.bins[s] = b.bins + I.bin_off + (long long)s * tiles * I.cap;
     }

@@ -28,7 +28,6 @@ struct SetupArgs {
     int max_tiles;          // tile slots per (item, sign)
     TriR* recR;
     TriS* recS;
-    TriF* recF;
     unsigned* counts;
     unsigned* bins;
     const float* fpos;      // subdivision surface: [pairs, nsign, n_verts, 3] positions, else null
@@ -47,7 +46,6 @@ struct TileArgs {
     int max_tiles;
     const TriR* recR;
     const TriS* recS;
-    const TriF* recF;
     unsigned* counts;
     const unsigned* bins;
     unsigned long long* stats;
@@ -153,7 +151,6 @@ struct BatchArgs {
     long long sign_blocks, setup_blocks, group_blocks, total_tiles;
     TriR* recR;
     TriS* recS;
-    TriF* recF;
     unsigned* counts;
     unsigned* bins;
     unsigned long long* stats;

@@ -177,6 +177,16 @@ dr_status dr_subdivide(const int32_t* tri, const float* corner_uv, int32_t n_ver
                        int32_t levels, int32_t* fine_tri, float* fine_corner_uv, int32_t* rowptr,
                        int32_t* cols, float* w);
 
+/* Adaptive bin capacity (default on): after an estimate whose largest tile
+ * bin exceeded bin_capacity (an overflowing tile falls back to testing
+ * every triangle, exact but slow), a later dr_estimate_grad* call raises
+ * the capacity to the next power of two above 1.5x that bin (at most 2^16),
+ * reallocating the bins once.  The figure is read back asynchronously, so
+ * the raise may come one call later.  Results never depend on it.
+ * dr_get_tuning reports the launch shape in force. */
+dr_status dr_set_adaptive_bins(dr_ctx* ctx, int32_t on);
+dr_status dr_get_tuning(const dr_ctx* ctx, dr_tuning* out);
+
 /* Counter word 3 of the sign stream of dr_estimate_grad (default 0): the
  * index of this scene in a batch, so that a scene stepped alone draws the
  * same signs as in a dr_batch. */

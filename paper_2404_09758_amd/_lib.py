@@ -90,6 +90,8 @@ SIGNATURES = {
     "dr_subdivide_sizes": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "dr_subdivide": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
+    "dr_set_adaptive_bins": (C.c_int, [_vp, C.c_int32]),
+    "dr_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
     "dr_decode_grad": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_float), C.c_int32, C.c_int32, _vp]),
     "dr_step": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, _vp, _vp, C.POINTER(C.c_float), C.c_int32,
                           C.POINTER(Optim)]),

@@ -171,6 +171,16 @@ class Context:
         self._call("dr_set_tuning", C.byref(tn))
         self.tuning = (tile_px, bin_capacity, items_per_launch)
 
+    def set_adaptive_bins(self, on=True):
+        """Raise the bin capacity after an estimate whose bins overflowed."""
+        self._call("dr_set_adaptive_bins", int(bool(on)))
+
+    def get_tuning(self):
+        """The launch shape in force: (tile_px, bin_capacity, items_per_launch)."""
+        t = L.Tuning()
+        self._call("dr_get_tuning", C.byref(t))
+        return (t.tile_px, t.bin_capacity, t.items_per_launch)
+
     def _eps(self, eps):
         e = list(eps) + [0.0] * (1 + L.MAX_TEX - len(eps))
         return _floats(e, 1 + L.MAX_TEX)

@@ -115,6 +115,12 @@ struct dr_ctx {
     int* tri_cols = nullptr;
     float* fpos = nullptr;          // tessellated positions per (pair, sign)
     long long fpos_slots = 0;
+    // adaptive bin capacity: the largest bin of the last estimate, read back
+    // asynchronously into pinned memory
+    int adapt = 1;
+    unsigned long long* h_seen = nullptr;
+    hipEvent_t ev_seen = nullptr;
+    bool seen_pending = false;
     Timer timer;
 };
 
@@ -415,6 +421,8 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
 extern "C" dr_status dr_destroy(dr_ctx* c) {
     if (!c) return DR_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
+    if (c->h_seen) (void)hipHostFree(c->h_seen);
+    if (c->ev_seen) (void)hipEventDestroy(c->ev_seen);
     void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
                     c->qtot, c->tri_rowptr, c->tri_cols, c->fpos};
     for (void* p : ptrs)
@@ -553,6 +561,40 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
 
 // ----------------------------------------------------------- estimate --
 
+// Bins that overflowed in an earlier estimate: raise the capacity to the
+// next power of two above 1.5x the largest bin seen.  The figure is read
+// back asynchronously; if it has not arrived yet the check waits for the
+// next call.  Results never depend on the capacity, only the speed does.
+static dr_status adapt_capacity(dr_ctx* c) {
+    if (!c->adapt || !c->seen_pending) return DR_OK;
+    if (hipEventQuery(c->ev_seen) != hipSuccess) {
+        (void)hipGetLastError();
+        return DR_OK;
+    }
+    c->seen_pending = false;
+    unsigned long long mb = *c->h_seen;
+    if (mb <= (unsigned long long)c->tune.bin_capacity) return DR_OK;
+    long long cap = 16;
+    while (cap < (long long)(mb + mb / 2 + 1) && cap < (1ll << 16)) cap *= 2;
+    if (cap <= c->tune.bin_capacity) return DR_OK;
+    dr_tuning t = c->tune;
+    t.bin_capacity = (int)cap;
+    return dr_set_tuning(c, &t);
+}
+
+static dr_status note_bins(dr_ctx* c) {
+    if (!c->adapt) return DR_OK;
+    if (!c->h_seen) {
+        HIPCHK(c, hipHostMalloc((void**)&c->h_seen, sizeof(unsigned long long), hipHostMallocDefault));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_seen, hipEventDisableTiming));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_seen, c->stats + ST_MAX_BIN, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_seen, c->stream));
+    c->seen_pending = true;
+    return DR_OK;
+}
+
 static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
                                  const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
                                  const float* eps, int64_t* Q, uint32_t* K, bool full, bool image) {
@@ -560,9 +602,13 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     if (!theta || !targets || !Q || !K || !views) return fail(c, DR_E_INVALID, "NULL array argument");
     if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
     if (n_pairs < 1 || n_pairs > 65535) return fail(c, DR_E_INVALID, "n_pairs must be in [1, 65535]");
-    int tile = c->tune.tile_px;
     dr_status s = check_eps(c, eps);
     if (s) return s;
+    s = device_guard(c);
+    if (s) return s;
+    s = adapt_capacity(c);
+    if (s) return s;
+    int tile = c->tune.tile_px;
     DViews dv;
     std::memset(&dv, 0, sizeof(dv));
     long long tgt_off = 0;
@@ -668,7 +714,7 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     fa.n_views = n_views;
     if (full) HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_broadcast(c->stream, fa); }));
     else HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
-    return DR_OK;
+    return note_bins(c);
 }
 
 extern "C" dr_status dr_estimate_grad(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
@@ -866,6 +912,19 @@ extern "C" dr_status dr_stats(dr_ctx* c, dr_stats_t* out) {
     out->saturations = h[ST_SATURATIONS];
     out->nonfinite = h[ST_NONFINITE];
     out->max_bin = h[ST_MAX_BIN];
+    return DR_OK;
+}
+
+extern "C" dr_status dr_set_adaptive_bins(dr_ctx* c, int32_t on) {
+    if (!c) return DR_E_INVALID;
+    c->adapt = on ? 1 : 0;
+    c->seen_pending = false;
+    return DR_OK;
+}
+
+extern "C" dr_status dr_get_tuning(const dr_ctx* c, dr_tuning* out) {
+    if (!c || !out) return DR_E_INVALID;
+    *out = c->tune;
     return DR_OK;
 }
 

@@ -502,3 +502,25 @@ def test_subdiv_argument_checks():
     sc.tex = [np.zeros((32, 32, 4), np.float32)]
     with pytest.raises(api.DRError):
         api.Context(sc, DEV)                                 # layered subdivision surfaces: unsupported
+
+
+def test_adaptive_bins_raise_capacity_and_keep_results():
+    """Bins of capacity 4 overflow; the context raises the capacity for the
+    next estimate (the largest bin is read back asynchronously) and the
+    results stay those of a context that keeps overflowing."""
+    sc = scene_by_name("lambert")
+    o = oracle.Oracle(sc)
+    tg = [dev(t) for t in targets_of(o, sc)]
+    th = dev(sc.flat_params())
+    ada = api.Context(sc, DEV, tuning=(16, 4, 0))
+    fix = api.Context(sc, DEV, tuning=(16, 4, 0))
+    fix.set_adaptive_bins(False)
+    overflows = []
+    for step in (1, 2, 3):
+        Qa, Ka = ada.estimate_grad(th, sc.views, tg, 9, step, 2, sc.eps)
+        Qf, Kf = fix.estimate_grad(th, sc.views, tg, 9, step, 2, sc.eps)
+        assert np.array_equal(host(Qa), host(Qf)) and np.array_equal(host(Ka), host(Kf))
+        overflows.append(ada.stats()["tile_overflows"])
+    assert overflows[0] > 0 and overflows[2] == overflows[1]       # no overflow after the raise
+    assert ada.get_tuning()[1] >= ada.stats()["max_bin"] and fix.get_tuning()[1] == 4
+    assert fix.stats()["tile_overflows"] > overflows[0]

@@ -115,3 +115,31 @@ def test_autotuned_shapes_give_identical_results():
     Q1, K1 = ctx.estimate_grad(th, sc.views, tg, 4, 2, 3, sc.eps)
     assert torch.equal(Q0, Q1) and torch.equal(K0, K1)
     assert ctx.stats()["tile_overflows"] == 0 or tuning[1] >= 16
+
+
+def test_paper_step_in_the_bench_launch_shape_matches_oracle():
+    """The benchmarked workload at full size (1024^2, 46 080 triangles, GGX
+    with three 1024^2 maps, 4 views x 8 pairs) in the bench's launch shape
+    (one batch scene, tile 16, capacity 256, graph-captured step): the Q
+    and K of one estimate equal the oracle's over all 32 items, and the
+    Adam step that follows equals the oracle's step, bit for bit."""
+    sc = S.make_paper()
+    o = oracle.Oracle(sc)
+    tg = [o.render(sc.flat_params(True), v)[0] for v in sc.views]
+    seed, step = sc.seed, 1
+    bt = batch.Batch([sc], sc.n_pairs, DEV, tile_px=16, seed=seed, first_step=step, bin_capacities=[256],
+                     targets=[[torch.tensor(t, device=DEV) for t in tg]])
+    bt.estimate()
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, seed, step, sc.n_pairs, sc.eps)
+    assert np.array_equal(host(bt.K[0]).view(np.uint32), Ko)
+    assert np.array_equal(host(bt.Q[0]), Qo)
+    # the graph-captured step recomputes the estimate and applies Adam
+    bt.Q[0].zero_()
+    bt.K[0].zero_()
+    bt.step(use_graph=True)
+    th_o, m_o, v_o = theta.copy(), np.zeros(o.d, np.float32), np.zeros(o.d, np.float32)
+    Qo2, Ko2 = Qo.copy(), Ko.copy()             # the same estimate (same seed, step and pairs)
+    o.step(th_o, m_o, v_o, step, Qo2, Ko2, sc.eps, sc.n_pairs, kind=S.OPT_ADAM, averaging=S.AVG_COUNT, lr=sc.lr)
+    assert np.array_equal(host(bt.theta[0]), th_o)
+    assert np.array_equal(host(bt.m[0]), m_o) and np.array_equal(host(bt.v[0]), v_o)

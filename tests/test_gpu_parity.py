@@ -524,3 +524,18 @@ def test_adaptive_bins_raise_capacity_and_keep_results():
     assert overflows[0] > 0 and overflows[2] == overflows[1]       # no overflow after the raise
     assert ada.get_tuning()[1] >= ada.stats()["max_bin"] and fix.get_tuning()[1] == 4
     assert fix.stats()["tile_overflows"] > overflows[0]
+
+
+def test_subdiv_full_size_one_pair_one_view_bit_exact():
+    """The subdivision workload at full size (2 000 control triangles ->
+    48 000, 1024^2, GGX with three 1024^2 maps), one (pair, view)."""
+    sc = S.make_subdiv()
+    sc.views = sc.views[:1]
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 5, 1, 1, sc.eps)
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 5, 1, 1, sc.eps)
+    assert np.array_equal(host(K).view(np.uint32), Ko)
+    assert np.array_equal(host(Q), Qo)

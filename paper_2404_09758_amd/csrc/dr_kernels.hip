@@ -375,9 +375,11 @@ __device__ __forceinline__ void ctrl_union_add(GroupTable<LOG2T>& tb, long long*
     }
 }
 
-// Tile kernels are asked for 6 resident waves per SIMD (at most 80 VGPRs):
-// the few spilled registers cost less than the added occupancy gains
-// (measured: 3.35 -> 3.28 ms per paper-scale step; 8 waves spill too much).
+// Opaque tile kernels of 8- and 16-pixel tiles are asked for 6 resident
+// waves per SIMD (at most 80 VGPRs): the few spilled registers cost less
+// than the added occupancy gains (measured: 3.35 -> 3.28 ms per paper-scale
+// step; 8 waves spill too much).  Larger tiles and deep buffers are held to
+// fewer waves by their LDS anyway.
 #define TILE_MIN_WAVES 6
 
 template <int TILE>
@@ -917,7 +919,8 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
 // body.  The job is built here, in the kernel itself, so that the argument
 // block is read in place from the kernel-argument segment.
 template <int TILE, int MODE, bool DEEP>
-__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE_MIN_WAVES) k_tile(TileArgs a) {
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, (DEEP || TILE > 16) ? 1 : TILE_MIN_WAVES)
+k_tile(TileArgs a) {
     using SH = std::conditional_t<DEEP, DeepShared<TILE, MODE>, TileShared<TILE, MODE>>;
     __shared__ SH S;
     constexpr int NS = SH::NS;
@@ -1185,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
 // launch: one workgroup per unit, units in the XCD-aware order of
 // xcd_tile(), items of the costliest scenes first.
 template <int TILE>
-__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE_MIN_WAVES) k_tile_b(BatchArgs b) {
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b(BatchArgs b) {
     __shared__ TileShared<TILE, 0> S;
     long long w = xcd_tile(blockIdx.x, gridDim.x);
     if (w >= b.total_tiles) return;

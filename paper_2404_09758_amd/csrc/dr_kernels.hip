@@ -495,26 +495,21 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         int px = 256 * x + 128, py = 256 * y + 128;
         unsigned id[NS];
         float rgb[NS][3], uv[NS][2];
-        int vids[NS][3];
-        Foot foot[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             unsigned long long k = inpix ? S.key[s][local] : ~0ull;
             id[s] = (k == ~0ull) ? DRD_BG : (unsigned)(k & 0xFFFFFFFFull);
             rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
             uv[s][0] = 0.0f; uv[s][1] = 0.0f;
-            vids[s][0] = vids[s][1] = vids[s][2] = -1;
-            foot[s].xa = foot[s].xb = foot[s].ya = foot[s].yb = 0;
-            foot[s].fx = foot[s].fy = 0.0f;
             if (id[s] != DRD_BG) {
                 TriR r = J.recR[s][id[s]];
                 TriS sh = J.recS[s][id[s]];
                 TriF fr;
                 if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id[s], fr);
                 float alpha;
+                Foot f0;
                 shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id[s], px, py, rgb[s], uv[s],
-                            foot[s], alpha);
-                vids[s][0] = sh.vid[0]; vids[s][1] = sh.vid[1]; vids[s][2] = sh.vid[2];
+                            f0, alpha);
             }
         }
         long long pix = (long long)y * vw.W + x;
@@ -555,26 +550,22 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 bool same = act && id[0] == id[1];
                 wave_ctrl<LOG2T>(S.table, J.Rp, J.K, sc, same, id[0], q);
                 if (act && !same) ctrl_union_add<LOG2T>(S.table, J.Rp, J.K, sc, id[0], id[1], q);
-            } else if (J.act_pos) {
-                // same triangle in both renders: combined per wave
-                bool same = act && id[0] == id[1];
-                if (same) {
+            } else if (J.act_pos && act) {
+                // the union of the two renders' triangles' vertices, each once
+                int v0[3] = {-1, -1, -1};
+                if (id[0] != DRD_BG) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)vids[0][k], q, 1u);
-                }
-                if (act && !same) {
-                    // the union of the two triangles' vertices, each once
-                    if (id[0] != DRD_BG) {
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)vids[0][k], q, 1u);
+                    for (int k = 0; k < 3; ++k) {
+                        v0[k] = sc.tri[3 * (long long)id[0] + k];
+                        table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
                     }
-                    if (id[1] != DRD_BG) {
+                }
+                if (id[1] != DRD_BG && id[1] != id[0]) {
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            int g = vids[1][k];
-                            bool dup = (g == vids[0][0]) || (g == vids[0][1]) || (g == vids[0][2]);
-                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
-                        }
+                    for (int k = 0; k < 3; ++k) {
+                        int g = sc.tri[3 * (long long)id[1] + k];
+                        bool dup = (g == v0[0]) || (g == v0[1]) || (g == v0[2]);
+                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
                     }
                 }
             }
@@ -588,7 +579,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                     for (int s = 0; s < NS; ++s) {
                         gs[s][0] = gs[s][1] = gs[s][2] = gs[s][3] = HASH_EMPTY;
                         if (id[s] == DRD_BG) continue;
-                        Foot f = (c == 0) ? foot[s] : footprint(uv[s][0], uv[s][1], W, H);
+                        Foot f = footprint(uv[s][0], uv[s][1], W, H);
                         if (sc.tex_mode == 1) {
                             int xn = (f.fx >= 0.5f) ? f.xb : f.xa;
                             int yn = (f.fy >= 0.5f) ? f.yb : f.ya;

@@ -376,10 +376,10 @@ __device__ __forceinline__ void ctrl_union_add(GroupTable<LOG2T>& tb, long long*
 }
 
 // Opaque tile kernels of 8- and 16-pixel tiles are asked for 6 resident
-// waves per SIMD (at most 80 VGPRs): the few spilled registers cost less
-// than the added occupancy gains (measured: 3.35 -> 3.28 ms per paper-scale
-// step; 8 waves spill too much).  Larger tiles and deep buffers are held to
-// fewer waves by their LDS anyway.
+// waves per SIMD (at most 80 VGPRs), which they meet without spilling
+// (measured per paper-scale step: 3.35 ms at 5 waves, 3.04 ms at 6; 7 and
+// 8 waves spill).  Larger tiles and deep buffers are held to fewer waves by
+// their LDS anyway.
 #define TILE_MIN_WAVES 6
 
 template <int TILE>

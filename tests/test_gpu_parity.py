@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2404_09758_amd import api
+from paper_2404_09758_amd import api, batch
 from paper_2404_09758_amd import scenes as S
 from tests import helpers as H
 
@@ -539,3 +539,29 @@ def test_subdiv_full_size_one_pair_one_view_bit_exact():
     Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 5, 1, 1, sc.eps)
     assert np.array_equal(host(K).view(np.uint32), Ko)
     assert np.array_equal(host(Q), Qo)
+
+
+def test_new_forms_edge_cases():
+    """An all-zero dL/dI gives Q = 0 and the contribution counts of the loss
+    form; a one-pixel view works for layered and subdivision scenes; the
+    batch form refuses layered and subdivision scenes."""
+    sc = scene_by_name("lambert")
+    o = oracle.Oracle(sc)
+    th = dev(sc.flat_params())
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    zero = [torch.zeros(int(v.height) * int(v.width) * 3, device=DEV) for v in sc.views]
+    Q, K = ctx.estimate_grad(th, sc.views, zero, 3, 1, 2, sc.eps, image_grad=True)
+    tg = [dev(t) for t in targets_of(o, sc)]
+    Q2, K2 = ctx.estimate_grad(th, sc.views, tg, 3, 1, 2, sc.eps)
+    assert int(host(Q).__abs__().sum()) == 0 and np.array_equal(host(K), host(K2))
+    for sc2 in (layered_scene("sphere2"), subdiv_scene("cc_unlit")):
+        o2 = oracle.Oracle(sc2)
+        v1 = S.look_at_view(1, 1, 0.0, 0.0)
+        c2 = api.Context(sc2, DEV, tuning=(8, 256, 0))
+        th2 = sc2.flat_params()
+        t1 = o2.render(sc2.flat_params(True), v1)[0]
+        Qo, Ko, _, _ = o2.estimate(th2, [v1], [t1], 1, 1, 2, sc2.eps)
+        Qg, Kg = c2.estimate_grad(dev(th2), [v1], [dev(t1)], 1, 1, 2, sc2.eps)
+        assert np.array_equal(host(Qg), Qo) and np.array_equal(host(Kg).view(np.uint32), Ko)
+        with pytest.raises(api.DRError):
+            batch.Batch([sc2], 1, DEV, tile_px=8, targets=[[dev(t1)]])

@@ -132,13 +132,38 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     recR[t] = r;
     recS[t] = sh;
     if (bx0 > bx1) return;
+    // Bin entries, one per tile the bbox touches.  Neighbouring triangles
+    // share tiles, so the wave's lanes bidding for one tile are served by a
+    // single counter atomic (the leader adds the group's size, each lane
+    // takes its rank in the group): same-address atomics no longer queue at
+    // one L2 channel.  Only the order of a bin's entries depends on this.
     int tx0 = bx0 / tile_px, tx1 = bx1 / tile_px, ty0 = by0 / tile_px, ty1 = by1 / tile_px;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            long long tile = (long long)ty * vw.tiles_x + tx;
-            unsigned k = atomicAdd(&counts[tile], 1u);
-            if (k < (unsigned)cap) bins[tile * cap + k] = (unsigned)t;
+    int ntx = tx1 - tx0 + 1;
+    int n = ntx * (ty1 - ty0 + 1);
+    int lane = threadIdx.x & 63;
+    unsigned long long below = (1ull << lane) - 1ull;
+    for (int i = 0;; ++i) {
+        bool has = i < n;
+        unsigned long long pend = __ballot(has);
+        if (pend == 0ull) break;
+        int tile = -1;
+        if (has) tile = (ty0 + i / ntx) * vw.tiles_x + tx0 + i % ntx;
+        while (pend) {
+            int leader = __ffsll(pend) - 1;
+            int lt = __shfl(tile, leader);
+            bool mine = has && tile == lt;
+            unsigned long long m = __ballot(mine);
+            unsigned base = 0u;
+            if (lane == leader) base = atomicAdd(&counts[lt], (unsigned)__popcll(m));
+            base = __shfl(base, leader);
+            if (mine) {
+                unsigned k = base + (unsigned)__popcll(m & below);
+                if (k < (unsigned)cap) bins[(long long)lt * cap + k] = (unsigned)t;
+                has = false;
+            }
+            pend &= ~m;
         }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {

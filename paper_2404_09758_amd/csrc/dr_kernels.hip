@@ -133,10 +133,11 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     recS[t] = sh;
     if (bx0 > bx1) return;
     // Bin entries, one per tile the bbox touches.  Neighbouring triangles
-    // share tiles, so the wave's lanes bidding for one tile are served by a
-    // single counter atomic (the leader adds the group's size, each lane
-    // takes its rank in the group): same-address atomics no longer queue at
-    // one L2 channel.  Only the order of a bin's entries depends on this.
+    // share tiles, so the wave's lanes bidding for one tile are grouped
+    // first (ballots only), then each group's leader adds the group's size
+    // to the tile's counter -- all leaders at once -- and each lane takes its
+    // rank in its group: same-address atomics no longer queue at one L2
+    // channel.  Only the order of a bin's entries depends on this.
     int tx0 = bx0 / tile_px, tx1 = bx1 / tile_px, ty0 = by0 / tile_px, ty1 = by1 / tile_px;
     int ntx = tx1 - tx0 + 1;
     int n = ntx * (ty1 - ty0 + 1);
@@ -148,20 +149,26 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
         if (pend == 0ull) break;
         int tile = -1;
         if (has) tile = (ty0 + i / ntx) * vw.tiles_x + tx0 + i % ntx;
+        int my_leader = lane;
+        unsigned rank = 0u, group = 0u;
         while (pend) {
             int leader = __ffsll(pend) - 1;
             int lt = __shfl(tile, leader);
             bool mine = has && tile == lt;
             unsigned long long m = __ballot(mine);
-            unsigned base = 0u;
-            if (lane == leader) base = atomicAdd(&counts[lt], (unsigned)__popcll(m));
-            base = __shfl(base, leader);
             if (mine) {
-                unsigned k = base + (unsigned)__popcll(m & below);
-                if (k < (unsigned)cap) bins[(long long)lt * cap + k] = (unsigned)t;
-                has = false;
+                my_leader = leader;
+                rank = (unsigned)__popcll(m & below);
             }
+            if (lane == leader) group = (unsigned)__popcll(m);
             pend &= ~m;
+        }
+        unsigned base = 0u;
+        if (has && my_leader == lane) base = atomicAdd(&counts[tile], group);
+        base = __shfl(base, my_leader);
+        if (has) {
+            unsigned k = base + rank;
+            if (k < (unsigned)cap) bins[(long long)tile * cap + k] = (unsigned)t;
         }
     }
 }

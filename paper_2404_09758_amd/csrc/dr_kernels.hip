@@ -1031,19 +1031,36 @@ __device__ __forceinline__ void for_params(const DScene& sc, long long g, Fn fn)
     }
 }
 
+// Q_i += sum_n s_i^(n) R_g^(n) for the parameters of group g, then R_g = 0.
+// Pairs are taken 8 at a time: the group's 8 sums are read once (not once
+// per parameter), a chunk that is all zero (the group was not seen by those
+// pairs) costs no sign reads, and only non-zero sums are cleared.
 __device__ __forceinline__ void fold_group(const DScene& sc, long long g, long long* __restrict__ R,
                                            const uint32_t* __restrict__ bits, int n_pairs, const float* eps,
                                            long long* __restrict__ Q) {
-    for_params(sc, g, [&](long long i, int b) {
-        if (eps[b] == 0.0f) return;
-        long long acc = 0;
-        for (int n = 0; n < n_pairs; ++n) {
-            long long r = R[(long long)n * sc.G + g];
-            acc += (sign_of(bits + (long long)n * sc.words, i) > 0) ? r : -r;
+    for (int n0 = 0; n0 < n_pairs; n0 += 8) {
+        long long r[8];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            r[j] = (n0 + j < n_pairs) ? R[(long long)(n0 + j) * sc.G + g] : 0;
+            any = any || r[j] != 0;
         }
-        if (acc != 0) Q[i] += acc;
-    });
-    for (int n = 0; n < n_pairs; ++n) R[(long long)n * sc.G + g] = 0;
+        if (!any) continue;
+        for_params(sc, g, [&](long long i, int b) {
+            if (eps[b] == 0.0f) return;
+            long long acc = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (r[j] == 0) continue;
+                acc += (sign_of(bits + (long long)(n0 + j) * sc.words, i) > 0) ? r[j] : -r[j];
+            }
+            if (acc != 0) Q[i] += acc;
+        });
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (r[j] != 0) R[(long long)(n0 + j) * sc.G + g] = 0;
+    }
 }
 
 // Full-image estimate: every parameter of an active block gets

@@ -234,6 +234,34 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // (an empty slot ends the cascade).  Every layer thus ends with the least
 // key that reached it, i.e. the l-th least key of the pixel, whatever the
 // interleaving of the lanes and waves.
+// Coverage, depth and the depth|id resolve of triangle t at pixel (x, y) of
+// the tile.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_px(const TriR& r, unsigned t, int x, int y, int px0, int py0,
+                                          unsigned long long* key, int L) {
+    int px = 256 * x + 128, py = 256 * y + 128;
+    bool cov;
+    if (r.flags & TRI_SMALL) {
+        cov = inside_small(r, px, py);
+    } else {
+        long long e0, e1, e2;
+        cov = inside(r, px, py, e0, e1, e2);
+    }
+    if (!cov) return;
+    float z = depth_at(r, px, py);
+    unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | t;
+    if constexpr (DEEP) {
+        unsigned long long* list = key + ((y - py0) * TILE + (x - px0)) * DRD_MAX_LAYERS;
+        for (int l = 0; l < L; ++l) {
+            unsigned long long old = atomicMin(&list[l], k);
+            if (old == ~0ull) break;
+            k = old > k ? old : k;
+        }
+    } else {
+        atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
+    }
+}
+
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, int py0, int lane,
                                            unsigned long long* key, int L) {
@@ -248,29 +276,66 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
         if (idx < n) {
             int dy = (int)(((unsigned)idx * m) >> 20);
             int dx = idx - dy * bw;
-            int x = x0 + dx, y = y0 + dy;
-            int px = 256 * x + 128, py = 256 * y + 128;
-            bool cov;
-            if (r.flags & TRI_SMALL) {
-                cov = inside_small(r, px, py);
-            } else {
-                long long e0, e1, e2;
-                cov = inside(r, px, py, e0, e1, e2);
-            }
-            if (cov) {
-                float z = depth_at(r, px, py);
-                unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | t;
-                if constexpr (DEEP) {
-                    unsigned long long* list = key + ((y - py0) * TILE + (x - px0)) * DRD_MAX_LAYERS;
-                    for (int l = 0; l < L; ++l) {
-                        unsigned long long old = atomicMin(&list[l], k);
-                        if (old == ~0ull) break;
-                        k = old > k ? old : k;
-                    }
-                } else {
-                    atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
-                }
-            }
+            raster_px<TILE, DEEP>(r, t, x0 + dx, y0 + dy, px0, py0, key, L);
+        }
+    }
+}
+
+// Lane-packed raster of up to 64 triangles held one per lane (mine: the
+// triangle index, valid for lanes below n): the triangles' clipped bounding
+// boxes are laid end to end (a prefix sum of their pixel counts) and each
+// pass gives one pixel of that sequence to every lane, which finds its
+// triangle by binary search over the prefix sums and reads the triangle's
+// data from its lane.  For small triangles this replaces one pass per
+// triangle, mostly idle lanes, with a pass per 64 covered candidates.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_packed(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
+                                              int py0, int lane, unsigned long long* key, int L) {
+    TriR r{};
+    int x0 = 0, y0 = 0, bw = 1, c = 0;
+    if ((unsigned)lane < n) {
+        r = R[mine];
+        int x1, y1;
+        x0 = max((int)r.bx0, px0); x1 = min((int)r.bx1, px0 + TILE - 1);
+        y0 = max((int)r.by0, py0); y1 = min((int)r.by1, py0 + TILE - 1);
+        if (x0 <= x1 && y0 <= y1) {
+            bw = x1 - x0 + 1;
+            c = bw * (y1 - y0 + 1);
+        }
+    }
+    int P = c;                                          // inclusive prefix sum over the lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int v = __shfl_up(P, off);
+        if (lane >= off) P += v;
+    }
+    int N = __shfl(P, 63);
+    int Pex = P - c;
+    unsigned m = ((1u << 20) + (unsigned)bw - 1u) / (unsigned)bw;
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        int sl = s0 + lane;
+        int lo = 0, hi = 63;                            // first lane whose prefix exceeds sl
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+            int mid = (lo + hi) >> 1;
+            int pm = __shfl(P, mid);
+            if (pm > sl) hi = mid;
+            else lo = mid + 1;
+        }
+        int j = lo;
+        TriR q;
+        q.X[0] = __shfl(r.X[0], j); q.X[1] = __shfl(r.X[1], j); q.X[2] = __shfl(r.X[2], j);
+        q.Y[0] = __shfl(r.Y[0], j); q.Y[1] = __shfl(r.Y[1], j); q.Y[2] = __shfl(r.Y[2], j);
+        q.z0 = __shfl(r.z0, j); q.zx = __shfl(r.zx, j); q.zy = __shfl(r.zy, j);
+        q.flags = (unsigned)__shfl((int)r.flags, j);
+        int qx0 = __shfl(x0, j), qy0 = __shfl(y0, j), qbw = __shfl(bw, j), qpex = __shfl(Pex, j);
+        unsigned qm = (unsigned)__shfl((int)m, j);
+        unsigned qt = (unsigned)__shfl((int)mine, j);
+        if (sl < N) {
+            int idx = sl - qpex;
+            int dy = (int)(((unsigned)idx * qm) >> 20);
+            int dx = idx - dy * qbw;
+            raster_px<TILE, DEEP>(q, qt, qx0 + dx, qy0 + dy, px0, py0, key, L);
         }
     }
 }
@@ -284,6 +349,12 @@ __device__ __forceinline__ void note_max_bin(unsigned long long* stats, unsigned
     if ((unsigned long long)c > seen) atomicMax(&stats[ST_MAX_BIN], (unsigned long long)c);
 }
 
+// A wave's batch of bin entries is rasterised lane-packed when it holds at
+// least this many triangles, one triangle per pass otherwise.
+#ifndef PACK_MIN_TRIS
+#define PACK_MIN_TRIS 8u
+#endif
+
 // Rasterise the cnt triangles of a tile's bin.  Wave w takes entries
 // w, w + nw, w + 2 nw, ...; it fetches 64 of them at once (one per lane),
 // so only the record load remains per triangle.
@@ -296,6 +367,10 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
         unsigned mine = k < cnt ? list[k] : 0u;
         unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
         if (n > 64u) n = 64u;
+        if (n >= PACK_MIN_TRIS) {
+            raster_packed<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L);
+            continue;
+        }
         for (unsigned j = 0; j < n; ++j) {
             unsigned t = __builtin_amdgcn_readlane(mine, j);
             TriR r = R[t];

@@ -3,13 +3,16 @@
 //
 // Pipeline of one estimate (Sec. 4.3, Alg. 1 and 2, Eq. 8-9):
 //   signs      Philox sign bits of every pair                  (shader P)
+//   subdiv     (subdivision surfaces only, Sec. 6.3) the tessellated
+//              vertex positions of every (pair, sign)
 //   setup      per (item, sign, triangle): perturb the three vertices,
 //              project, snap, build the raster record and append the
 //              triangle to the bins of the tiles its bbox touches
 //   tile       per (item, tile): rasterise the + and - scenes into LDS
-//              depth|id keys (64-bit atomic min), shade both winners,
-//              form the per-pixel loss difference and scatter it to the
-//              union of the pixel's contribution groups     (R and G fused)
+//              depth|id keys (64-bit atomic min; the L nearest keys for
+//              semi-transparent scenes), shade (and composite), form the
+//              per-pixel difference and scatter it to the union of the
+//              pixel's contribution groups                  (R and G fused)
 //   fold       Q_i += sum_n s_i^(n) R^(n)_g(i): the per-group sums of each
 //              pair become per-parameter fixed-point sums
 //   step       decode, per-parameter average, Adam / SGD    (shader D)

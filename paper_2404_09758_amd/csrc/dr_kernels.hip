@@ -284,16 +284,17 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
     }
 }
 
-// Lane-packed raster of up to 64 triangles held one per lane (mine: the
-// triangle index, valid for lanes below n): the triangles' clipped bounding
-// boxes are laid end to end (a prefix sum of their pixel counts) and each
-// pass gives one pixel of that sequence to every lane, which finds its
-// triangle by binary search over the prefix sums and reads the triangle's
-// data from its lane.  For small triangles this replaces one pass per
-// triangle, mostly idle lanes, with a pass per 64 covered candidates.
+// Raster of up to 64 triangles held one per lane (mine: the triangle
+// index, valid for lanes below n).  Lane-packed when that takes fewer
+// passes: the triangles' clipped bounding boxes are laid end to end (a
+// prefix sum of their pixel counts) and each pass gives one pixel of that
+// sequence to every lane, which finds its triangle by binary search over
+// the prefix sums and reads the triangle's data from its lane.  For small
+// triangles this replaces one pass per triangle, mostly idle lanes, with a
+// pass per 64 candidates; large triangles keep a pass per 64 pixels of each.
 template <int TILE, bool DEEP>
-__device__ __forceinline__ void raster_packed(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
-                                              int py0, int lane, unsigned long long* key, int L) {
+__device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
+                                             int py0, int lane, unsigned long long* key, int L) {
     TriR r{};
     int x0 = 0, y0 = 0, bw = 1, c = 0;
     if ((unsigned)lane < n) {
@@ -306,13 +307,28 @@ __device__ __forceinline__ void raster_packed(const TriR* __restrict__ R, unsign
             c = bw * (y1 - y0 + 1);
         }
     }
-    int P = c;                                          // inclusive prefix sum over the lanes
+    int P = c;                                          // inclusive prefix sums over the lanes
+    int T = (c + 63) >> 6;                              // passes of the per-triangle loop
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        int v = __shfl_up(P, off);
-        if (lane >= off) P += v;
+        int v = __shfl_up(P, off), w = __shfl_up(T, off);
+        if (lane >= off) { P += v; T += w; }
     }
     int N = __shfl(P, 63);
+    int passes_tri = __shfl(T, 63);
+    int passes_packed = (N + 63) >> 6;
+    if (2 * passes_packed >= passes_tri) {
+        // one triangle at a time, its record read from the lane that holds it
+        const int* mw = reinterpret_cast<const int*>(&r);
+        for (unsigned j = 0; j < n; ++j) {
+            TriR q;
+            int* qw = reinterpret_cast<int*>(&q);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) qw[k] = __builtin_amdgcn_readlane(mw[k], j);
+            raster_tri<TILE, DEEP>(q, __builtin_amdgcn_readlane(mine, j), px0, py0, lane, key, L);
+        }
+        return;
+    }
     int Pex = P - c;
     unsigned m = ((1u << 20) + (unsigned)bw - 1u) / (unsigned)bw;
     for (int s0 = 0; s0 < N; s0 += 64) {
@@ -352,8 +368,9 @@ __device__ __forceinline__ void note_max_bin(unsigned long long* stats, unsigned
     if ((unsigned long long)c > seen) atomicMax(&stats[ST_MAX_BIN], (unsigned long long)c);
 }
 
-// A wave's batch of bin entries is rasterised lane-packed when it holds at
-// least this many triangles, one triangle per pass otherwise.
+// A wave's batch of bin entries holding at least this many triangles goes
+// through raster_batch (lane-packed when that saves passes); smaller batches
+// take one triangle per pass.
 #ifndef PACK_MIN_TRIS
 #define PACK_MIN_TRIS 8u
 #endif
@@ -371,7 +388,7 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
         unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
         if (n > 64u) n = 64u;
         if (n >= PACK_MIN_TRIS) {
-            raster_packed<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L);
+            raster_batch<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L);
             continue;
         }
         for (unsigned j = 0; j < n; ++j) {

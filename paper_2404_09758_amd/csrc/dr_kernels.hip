@@ -292,6 +292,9 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
 // the prefix sums and reads the triangle's data from its lane.  For small
 // triangles this replaces one pass per triangle, mostly idle lanes, with a
 // pass per 64 candidates; large triangles keep a pass per 64 pixels of each.
+// A packed pass costs more, so packing is taken when it saves a quarter of
+// the passes (measured against always and never packing on the mesh, the
+// 64-scene batch and the triangle soups).
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
                                              int py0, int lane, unsigned long long* key, int L) {
@@ -317,7 +320,7 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
     int N = __shfl(P, 63);
     int passes_tri = __shfl(T, 63);
     int passes_packed = (N + 63) >> 6;
-    if (2 * passes_packed >= passes_tri) {
+    if (4 * passes_packed >= 3 * passes_tri) {
         // one triangle at a time, its record read from the lane that holds it
         const int* mw = reinterpret_cast<const int*>(&r);
         for (unsigned j = 0; j < n; ++j) {

@@ -237,56 +237,92 @@ __device__ __forceinline__ Foot footprint(float u, float v, int W, int H) {
     return f;
 }
 
-// The C <= 4 consecutive parameters [i, i + C) of one texel, perturbed as by
-// pval: the values are read together (C = 3 and 4 as one vector load) and
-// the sign bits from the one or two words that hold them.
-__device__ __forceinline__ void texel_pvals(const float* __restrict__ th, long long i, int C, float e,
-                                            const uint32_t* __restrict__ pb, float sgn, float* x) {
-    if (C == 3) {
-        x[0] = th[i]; x[1] = th[i + 1]; x[2] = th[i + 2]; x[3] = 0.0f;
-    } else if (C == 1) {
-        x[0] = th[i]; x[1] = 0.0f; x[2] = 0.0f; x[3] = 0.0f;
-    } else {
+// Global-memory views of device pointers (address space 1).  Loads and
+// atomics through them compile to global_* instructions instead of flat_*
+// ones, so the compiler can wait on each request by itself instead of on
+// all outstanding memory and LDS traffic together.
+#define DRD_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const DRD_GLOBAL T*)p;
+#else
+    return *p;             // host pass: parsed, never run
+#endif
+}
+
+// Bilinear sample of one texture with C channels per texel (C consecutive
+// parameters per texel), perturbed as by pval.  All four texels' values and
+// sign words are requested before any is used.  The perturbed value is
+// x + (s_i ? -es : es) with es = +-eps by the render's sign: x - y and
+// x + (-y) are the same IEEE operation, so this equals pval's result.
+template <int C>
+__device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const DRD_GLOBAL uint32_t* pb,
+                                              int words, long long base, int W, float e, float sgn, const Foot& f,
+                                              float* out) {
+    const DRD_GLOBAL float* tt = th + base;
+    const bool pert = pb != nullptr && e != 0.0f;
+    const DRD_GLOBAL uint32_t* pw = pb + (base >> 5);
+    unsigned bb = (unsigned)(base & 31), nw = (unsigned)(words - (int)(base >> 5));
+    float es = (sgn > 0.0f) ? e : -e;
+    float wx[2] = {1.0f - f.fx, f.fx};
+    float acc[C];
+    // row by row (ya, then yb), two texels each: the weighted sum keeps its
+    // order ((w00 t00 + w10 t10) + w01 t01) + w11 t11
 #pragma unroll
-        for (int c = 0; c < 4; ++c) x[c] = (c < C) ? th[i + c] : 0.0f;
-    }
-    if (pb == nullptr || e == 0.0f) return;
-    unsigned b = (unsigned)(i & 31);
-    long long wi = i >> 5;
-    unsigned long long w = pb[wi];
-    if (b + (unsigned)C > 32u) w |= (unsigned long long)pb[wi + 1] << 32;
-    w >>= b;
+    for (int row = 0; row < 2; ++row) {
+        int yy = row ? f.yb : f.ya;
+        float wy = row ? f.fy : 1.0f - f.fy;
+        // texel offsets within the texture: W, H <= 32768 and C <= 4 keep
+        // them below 2^32
+        unsigned o[2];
+        o[0] = ((unsigned)yy * (unsigned)W + (unsigned)f.xa) * C;
+        o[1] = ((unsigned)yy * (unsigned)W + (unsigned)f.xb) * C;
+        float x[2][C];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        float se = ((w >> c) & 1ull) ? -e : e;
-        x[c] = (sgn > 0.0f) ? (x[c] + se) : (x[c] - se);
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[k][c] = tt[(unsigned long long)o[k] + c];
+        if (pert) {
+            // parameter base + o has its sign at bit (base + o) mod 32 of
+            // word (base + o) / 32; the texel's C bits may run into the next
+            // word (read only while it exists)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                unsigned r = (o[k] & 31u) + bb;
+                unsigned wi = (o[k] >> 5) + (r >> 5);
+                unsigned lo = pw[wi];
+                unsigned win = lo >> (r & 31u);
+                if (C > 1) win = __builtin_amdgcn_alignbit(pw[wi + 1u < nw ? wi + 1u : wi], lo, r & 31u);
+#pragma unroll
+                for (int c = 0; c < C; ++c) x[k][c] = x[k][c] + (((win >> c) & 1u) ? -es : es);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float t0 = (wx[0] * wy) * x[0][c], t1 = (wx[1] * wy) * x[1][c];
+            acc[c] = row ? ((acc[c] + t0) + t1) : (t0 + t1);
+        }
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = acc[c];
 }
 
 // Bilinear sample of texture t of the perturbed scene (theta + sgn s eps)
-// over a precomputed footprint.  out has room for 4 channels; the channel
-// loop is unrolled to 4 so that out stays in registers.
+// over a precomputed footprint.  out has room for 4 channels; channels at
+// and beyond the texture's count keep their values.
 __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __restrict__ th,
                                            const uint32_t* __restrict__ pb, float e, float sgn, int t,
                                            const Foot& f, float* out) {
     int W = sc.tex_w[t], C = sc.tex_c[t];
     long long base = sc.tex_off[t];
-    float w00 = (1.0f - f.fx) * (1.0f - f.fy);
-    float w10 = f.fx * (1.0f - f.fy);
-    float w01 = (1.0f - f.fx) * f.fy;
-    float w11 = f.fx * f.fy;
-    long long i00 = base + ((long long)f.ya * W + f.xa) * C;
-    long long i10 = base + ((long long)f.ya * W + f.xb) * C;
-    long long i01 = base + ((long long)f.yb * W + f.xa) * C;
-    long long i11 = base + ((long long)f.yb * W + f.xb) * C;
-    float t00[4], t10[4], t01[4], t11[4];
-    texel_pvals(th, i00, C, e, pb, sgn, t00);
-    texel_pvals(th, i10, C, e, pb, sgn, t10);
-    texel_pvals(th, i01, C, e, pb, sgn, t01);
-    texel_pvals(th, i11, C, e, pb, sgn, t11);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        if (c < C) out[c] = ((w00 * t00[c] + w10 * t10[c]) + w01 * t01[c]) + w11 * t11[c];
+    const DRD_GLOBAL float* gth = (const DRD_GLOBAL float*)th;
+    const DRD_GLOBAL uint32_t* gpb = (const DRD_GLOBAL uint32_t*)pb;
+    if (C == 3) sample_texels<3>(gth, gpb, sc.words, base, W, e, sgn, f, out);
+    else if (C == 1) sample_texels<1>(gth, gpb, sc.words, base, W, e, sgn, f, out);
+    else if (C == 4) sample_texels<4>(gth, gpb, sc.words, base, W, e, sgn, f, out);
+    else sample_texels<2>(gth, gpb, sc.words, base, W, e, sgn, f, out);
 }
 
 __device__ __forceinline__ void nrm3(float* x) {
@@ -311,7 +347,8 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
 
 // Face frame of a triangle from its perturbed corners p (original order)
 // and corner UVs: the unit face normal and, for GGX, the tangent frame.
-__device__ __forceinline__ void face_frame(int shading, const float* p, const float* cuv, TriF& F) {
+__device__ __forceinline__ void face_frame(int shading, const float* p, const float* cuv_, TriF& F) {
+    const DRD_GLOBAL float* cuv = (const DRD_GLOBAL float*)cuv_;
     float e1v[3], e2v[3], nf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) { e1v[c] = p[3 + c] - p[c]; e2v[c] = p[6 + c] - p[c]; }
@@ -360,7 +397,7 @@ __device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const
     float S = (pc0 + pc1) + pc2;
     float iS = 1.0f / S;
     bool sw = (r.flags & TRI_SWAPPED) != 0u;
-    const float* cuv = sc.cuv + 6 * (long long)t;
+    const DRD_GLOBAL float* cuv = (const DRD_GLOBAL float*)(sc.cuv + 6 * (long long)t);
     float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];
     float un1 = sw ? cu2 : cu1, vn1 = sw ? cv2 : cv1, un2 = sw ? cu1 : cu2, vn2 = sw ? cv1 : cv2;
     Attr a;
@@ -480,7 +517,8 @@ __device__ __forceinline__ long long quantize(float delta, int& flag) {
 // downstream loss with respect to the pixel's colour and the difference is
 // <g, I+ - I->, the first-order change of that loss, so that the estimator
 // approximates the vector-Jacobian product of the render.
-__device__ __forceinline__ float pixel_delta(const float* p, const float* m, const float* t, int img) {
+__device__ __forceinline__ float pixel_delta(const float* p, const float* m, const float* t_, int img) {
+    const DRD_GLOBAL float* t = (const DRD_GLOBAL float*)t_;
     float t0 = t[0], t1 = t[1], t2 = t[2];
     if (img) {
         float d0 = p[0] - m[0], d1 = p[1] - m[1], d2 = p[2] - m[2];

@@ -301,7 +301,7 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
     TriR r{};
     int x0 = 0, y0 = 0, bw = 1, c = 0;
     if ((unsigned)lane < n) {
-        r = R[mine];
+        r = gload(&R[mine]);
         int x1, y1;
         x0 = max((int)r.bx0, px0); x1 = min((int)r.bx1, px0 + TILE - 1);
         y0 = max((int)r.by0, py0); y1 = min((int)r.by1, py0 + TILE - 1);
@@ -387,7 +387,7 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
                                            int py0, unsigned long long* key, int L) {
     for (unsigned base = (unsigned)wave; base < cnt; base += 64u * (unsigned)nw) {
         unsigned k = base + (unsigned)lane * (unsigned)nw;
-        unsigned mine = k < cnt ? list[k] : 0u;
+        unsigned mine = k < cnt ? gload(&list[k]) : 0u;
         unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
         if (n > 64u) n = 64u;
         if (n >= PACK_MIN_TRIS) {
@@ -396,7 +396,7 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
         }
         for (unsigned j = 0; j < n; ++j) {
             unsigned t = __builtin_amdgcn_readlane(mine, j);
-            TriR r = R[t];
+            TriR r = gload(&R[t]);
             raster_tri<TILE, DEEP>(r, t, px0, py0, lane, key, L);
         }
     }
@@ -437,8 +437,10 @@ __device__ __forceinline__ void unpack_sc(unsigned long long w, long long& q, un
 
 __device__ __forceinline__ void global_add(long long* __restrict__ Rp, unsigned* __restrict__ K, long long g,
                                            long long q, unsigned c) {
-    if (q != 0) atomicAdd((unsigned long long*)&Rp[g], (unsigned long long)q);
-    atomicAdd(&K[g], c);
+    if (q != 0)
+        __hip_atomic_fetch_add((DRD_GLOBAL unsigned long long*)&Rp[g], (unsigned long long)q, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add((DRD_GLOBAL unsigned*)&K[g], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int LOG2T>
@@ -599,7 +601,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         } else {
             // bin overflow: test every triangle against this tile
             for (int t = wave; t < sc.n_tris; t += NW) {
-                TriR r = R[t];
+                TriR r = gload(&R[t]);
                 if (!(r.flags & TRI_VALID)) continue;
                 raster_tri<TILE, false>(r, (unsigned)t, px0, py0, lane, S.key[s], 1);
             }
@@ -632,8 +634,8 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             rgb[s][0] = 0.0f; rgb[s][1] = 0.0f; rgb[s][2] = 0.0f;
             uv[s][0] = 0.0f; uv[s][1] = 0.0f;
             if (id[s] != DRD_BG) {
-                TriR r = J.recR[s][id[s]];
-                TriS sh = J.recS[s][id[s]];
+                TriR r = gload(&J.recR[s][id[s]]);
+                TriS sh = gload(&J.recS[s][id[s]]);
                 TriF fr;
                 if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id[s], fr);
                 float alpha;
@@ -686,14 +688,14 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 if (id[0] != DRD_BG) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        v0[k] = sc.tri[3 * (long long)id[0] + k];
+                        v0[k] = gload(&sc.tri[3 * (long long)id[0] + k]);
                         table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
                     }
                 }
                 if (id[1] != DRD_BG && id[1] != id[0]) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        int g = sc.tri[3 * (long long)id[1] + k];
+                        int g = gload(&sc.tri[3 * (long long)id[1] + k]);
                         bool dup = (g == v0[0]) || (g == v0[1]) || (g == v0[2]);
                         if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
                     }
@@ -854,7 +856,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                                    S.key[s], L);
         } else {
             for (int t = wave; t < sc.n_tris; t += NW) {
-                TriR r = R[t];
+                TriR r = gload(&R[t]);
                 if (!(r.flags & TRI_VALID)) continue;
                 raster_tri<TILE, true>(r, (unsigned)t, px0, py0, lane, S.key[s], L);
             }
@@ -892,8 +894,8 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
             float uv[2] = {0.0f, 0.0f};
             if (id != DRD_BG) {
                 any = true;
-                TriR r = J.recR[s][id];
-                TriS sh = J.recS[s][id];
+                TriR r = gload(&J.recR[s][id]);
+                TriS sh = gload(&J.recS[s][id]);
                 TriF fr;
                 if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id, fr);
                 float c[3], al;

@@ -237,6 +237,21 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // (an empty slot ends the cascade).  Every layer thus ends with the least
 // key that reached it, i.e. the l-th least key of the pixel, whatever the
 // interleaving of the lanes and waves.
+// Offer depth|id key k to pixel li of the tile.
+template <bool DEEP>
+__device__ __forceinline__ void insert_key(unsigned long long* key, int li, unsigned long long k, int L) {
+    if constexpr (DEEP) {
+        unsigned long long* list = key + li * DRD_MAX_LAYERS;
+        for (int l = 0; l < L; ++l) {
+            unsigned long long old = atomicMin(&list[l], k);
+            if (old == ~0ull) break;
+            k = old > k ? old : k;
+        }
+    } else {
+        atomicMin(&key[li], k);
+    }
+}
+
 // Coverage, depth and the depth|id resolve of triangle t at pixel (x, y) of
 // the tile.
 template <int TILE, bool DEEP>
@@ -252,17 +267,7 @@ __device__ __forceinline__ void raster_px(const TriR& r, unsigned t, int x, int 
     }
     if (!cov) return;
     float z = depth_at(r, px, py);
-    unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | t;
-    if constexpr (DEEP) {
-        unsigned long long* list = key + ((y - py0) * TILE + (x - px0)) * DRD_MAX_LAYERS;
-        for (int l = 0; l < L; ++l) {
-            unsigned long long old = atomicMin(&list[l], k);
-            if (old == ~0ull) break;
-            k = old > k ? old : k;
-        }
-    } else {
-        atomicMin(&key[(y - py0) * TILE + (x - px0)], k);
-    }
+    insert_key<DEEP>(key, (y - py0) * TILE + (x - px0), ((unsigned long long)__float_as_uint(z) << 32) | t, L);
 }
 
 template <int TILE, bool DEEP>
@@ -284,6 +289,100 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
     }
 }
 
+// Per-wave LDS staging of a batch of small triangles for the packed raster
+// (80 B each): edge k as an integer plane over the triangle's clipped
+// bounding box, e_k(dx, dy) = a_k dx + b_k dy + c_k at pixel (x0 + dx,
+// y0 + dy), the depth plane's offsets and the key index of the box corner.
+struct __align__(16) PTri {
+    int b[3];            // 256 dX_k: change of edge k per pixel row
+    int a[3];            // -256 dY_k: change of edge k per pixel column
+    int c[3];            // edge k at the corner pixel, plus 1 on a top-left edge
+    int dz[2];           // corner pixel centre minus vertex 0, in subpixels
+    float z0, zx, zy;
+    unsigned t;
+    int off0;            // key index of the corner pixel
+    int bw;              // box width
+    unsigned m;          // ceil(2^20 / bw)
+    int pex;             // the triangle's first slot in the packed sequence
+    int pad;
+};
+
+struct RasterStage {
+    PTri tri[64];
+    int mark[64];
+};
+
+static_assert(sizeof(PTri) == 80, "PTri layout");
+
+// Packed raster of a batch whose triangles are all TRI_SMALL, through the
+// wave's LDS stage.  The batch's non-empty triangles are stored by rank;
+// each pass marks the slots where a triangle begins, and a lane's triangle
+// is then the number of triangles begun up to its slot (a ballot and a
+// lane-masked bit count) -- one LDS read of the staged record instead of a
+// binary search and a shuffle per field.  Edge values are exact: for a
+// TRI_SMALL triangle every term is below 2^30 in magnitude, so the 32-bit
+// sums equal the 64-bit ones, and e > 0 || (e == 0 && top-left) is
+// e + [top-left] > 0.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, unsigned t, int c, int x0, int y0,
+                                              int bw, int pex, int N, int px0, int py0, int lane,
+                                              unsigned long long* key, int L) {
+    unsigned long long nz = __ballot(c > 0);
+    if (c > 0) {
+        int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(nz >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)nz, 0u));
+        PTri q;
+        int cx = 256 * x0 + 128, cy = 256 * y0 + 128;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int ia = (k + 1) % 3, ib = (k + 2) % 3;
+            int dX = r.X[ib] - r.X[ia], dY = r.Y[ib] - r.Y[ia];
+            q.b[k] = 256 * dX;
+            q.a[k] = -256 * dY;
+            q.c[k] = (__mul24(dX, cy - r.Y[ia]) - __mul24(dY, cx - r.X[ia])) + (int)((r.flags >> (k + 1)) & 1u);
+        }
+        q.dz[0] = cx - r.X[0];
+        q.dz[1] = cy - r.Y[0];
+        q.z0 = r.z0; q.zx = r.zx; q.zy = r.zy;
+        q.t = t;
+        q.off0 = (y0 - py0) * TILE + (x0 - px0);
+        q.bw = bw;
+        q.m = ((1u << 20) + (unsigned)bw - 1u) / (unsigned)bw;     // exact for bw <= 32, idx < 1024
+        q.pex = pex;
+        q.pad = 0;
+        st->tri[rank] = q;
+    }
+    __builtin_amdgcn_wave_barrier();
+    int base = 0;                                       // triangles begun before this pass
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        st->mark[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (c > 0 && pex >= s0 && pex < s0 + 64) st->mark[pex - s0] = 1;
+        __builtin_amdgcn_wave_barrier();
+        int f = st->mark[lane];
+        unsigned long long M = __ballot(f != 0);
+        int rr = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)M, 0u)) + f - 1;
+        base += __popcll(M);
+        int sl = s0 + lane;
+        if (sl < N) {
+            PTri q = st->tri[rr];
+            int idx = sl - q.pex;
+            int dy = (int)(((unsigned)idx * q.m) >> 20);
+            int dx = idx - dy * q.bw;
+            int e0 = (__mul24(q.a[0], dx) + __mul24(q.b[0], dy)) + q.c[0];
+            int e1 = (__mul24(q.a[1], dx) + __mul24(q.b[1], dy)) + q.c[1];
+            int e2 = (__mul24(q.a[2], dx) + __mul24(q.b[2], dy)) + q.c[2];
+            if (min(e0, min(e1, e2)) > 0) {
+                float z = (q.z0 + q.zx * (float)(256 * dx + q.dz[0])) + q.zy * (float)(256 * dy + q.dz[1]);
+                if (!(z > 0.0f)) z = 0.0f;
+                insert_key<DEEP>(key, q.off0 + dy * TILE + dx,
+                                 ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Raster of up to 64 triangles held one per lane (mine: the triangle
 // index, valid for lanes below n).  Lane-packed when that takes fewer
 // passes: the triangles' clipped bounding boxes are laid end to end (a
@@ -297,7 +396,8 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
 // 64-scene batch and the triangle soups).
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
-                                             int py0, int lane, unsigned long long* key, int L) {
+                                             int py0, int lane, unsigned long long* key, int L,
+                                             RasterStage* stage) {
     TriR r{};
     int x0 = 0, y0 = 0, bw = 1, c = 0;
     if ((unsigned)lane < n) {
@@ -320,6 +420,11 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
     int N = __shfl(P, 63);
     int passes_tri = __shfl(T, 63);
     int passes_packed = (N + 63) >> 6;
+    if (stage != nullptr && passes_packed <= passes_tri &&
+        __ballot(c > 0 && !(r.flags & TRI_SMALL)) == 0ull) {
+        raster_staged<TILE, DEEP>(stage, r, mine, c, x0, y0, bw, P - c, N, px0, py0, lane, key, L);
+        return;
+    }
     if (4 * passes_packed >= 3 * passes_tri) {
         // one triangle at a time, its record read from the lane that holds it
         const int* mw = reinterpret_cast<const int*>(&r);
@@ -384,14 +489,14 @@ __device__ __forceinline__ void note_max_bin(unsigned long long* stats, unsigned
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, unsigned cnt,
                                            const TriR* __restrict__ R, int wave, int nw, int lane, int px0,
-                                           int py0, unsigned long long* key, int L) {
+                                           int py0, unsigned long long* key, int L, RasterStage* stage) {
     for (unsigned base = (unsigned)wave; base < cnt; base += 64u * (unsigned)nw) {
         unsigned k = base + (unsigned)lane * (unsigned)nw;
         unsigned mine = k < cnt ? gload(&list[k]) : 0u;
         unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
         if (n > 64u) n = 64u;
         if (n >= PACK_MIN_TRIS) {
-            raster_batch<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L);
+            raster_batch<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L, stage);
             continue;
         }
         for (unsigned j = 0; j < n; ++j) {
@@ -563,7 +668,11 @@ struct TileShared {
     static constexpr int NS = (MODE == 0 || MODE == 3) ? 2 : 1;
     static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
     unsigned long long key[NS][NPIX];
-    GroupTable<LOG2T> table;
+    // the raster's per-wave stages, then (estimate) the group table
+    union {
+        RasterStage stage[TB / 64];
+        GroupTable<LOG2T> table;
+    } u;
     double red[MODE == 2 ? TB : 1];
     long long qred[MODE == 3 ? TB : 1];
 };
@@ -582,12 +691,6 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int j = tid; j < NS * NPIX; j += TB) (&S.key[0][0])[j] = ~0ull;
-    if constexpr (MODE == 0) {
-        for (int j = tid; j < TSIZE; j += TB) {
-            S.table.key[j] = HASH_EMPTY;
-            S.table.sum[j] = 0ull;
-        }
-    }
     __syncthreads();
 
     unsigned cnt[NS];
@@ -597,7 +700,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         const TriR* __restrict__ R = J.recR[s];
         if (cnt[s] <= (unsigned)J.cap) {
             raster_bin<TILE, false>(J.bins[s] + (long long)J.tile * J.cap, cnt[s], R, wave, NW, lane, px0, py0,
-                                    S.key[s], 1);
+                                    S.key[s], 1, &S.u.stage[wave]);
         } else {
             // bin overflow: test every triangle against this tile
             for (int t = wave; t < sc.n_tris; t += NW) {
@@ -614,6 +717,13 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             J.counts[s][J.tile] = 0u;            // leave the bin empty for the next use
             if (cnt[s] > (unsigned)J.cap) atomicAdd(&J.stats[ST_OVERFLOWS], 1ull);
             note_max_bin(J.stats, cnt[s]);
+        }
+    }
+    if constexpr (MODE == 0) {
+        // the stages are done with: the group table takes their place
+        for (int j = tid; j < TSIZE; j += TB) {
+            S.u.table.key[j] = HASH_EMPTY;
+            S.u.table.sum[j] = 0ull;
         }
     }
 
@@ -670,6 +780,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 J.out_uv[2 * pix + 1] = uv[0][1];
             }
         } else {
+            if (j == 0) __syncthreads();         // the group table is cleared
             // an empty contribution set (background in both renders) adds nothing
             bool act = inpix && (id[0] != DRD_BG || id[1] != DRD_BG) && J.any_act;
             long long q = 0;
@@ -680,8 +791,8 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             }
             if (J.act_pos && sc.n_ctrl > 0) {
                 bool same = act && id[0] == id[1];
-                wave_ctrl<LOG2T>(S.table, J.Rp, J.K, sc, same, id[0], q);
-                if (act && !same) ctrl_union_add<LOG2T>(S.table, J.Rp, J.K, sc, id[0], id[1], q);
+                wave_ctrl<LOG2T>(S.u.table, J.Rp, J.K, sc, same, id[0], q);
+                if (act && !same) ctrl_union_add<LOG2T>(S.u.table, J.Rp, J.K, sc, id[0], id[1], q);
             } else if (J.act_pos && act) {
                 // the union of the two renders' triangles' vertices, each once
                 int v0[3] = {-1, -1, -1};
@@ -689,7 +800,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         v0[k] = gload(&sc.tri[3 * (long long)id[0] + k]);
-                        table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
+                        table_add<LOG2T>(S.u.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
                     }
                 }
                 if (id[1] != DRD_BG && id[1] != id[0]) {
@@ -697,7 +808,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                     for (int k = 0; k < 3; ++k) {
                         int g = gload(&sc.tri[3 * (long long)id[1] + k]);
                         bool dup = (g == v0[0]) || (g == v0[1]) || (g == v0[2]);
-                        if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)g, q, 1u);
+                        if (!dup) table_add<LOG2T>(S.u.table, J.Rp, J.K, (unsigned)g, q, 1u);
                     }
                 }
             }
@@ -738,7 +849,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                                 for (int j2 = 0; j2 < 4; ++j2)
                                     if (gs[0][j2] == g) dup = true;
                             }
-                            if (!dup) table_add<LOG2T>(S.table, J.Rp, J.K, g, q, 1u);
+                            if (!dup) table_add<LOG2T>(S.u.table, J.Rp, J.K, g, q, 1u);
                         }
                 }
             }
@@ -767,11 +878,11 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     if constexpr (MODE == 0) {
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
-            unsigned g = S.table.key[j];
+            unsigned g = S.u.table.key[j];
             if (g != HASH_EMPTY) {
                 long long q;
                 unsigned c;
-                unpack_sc(S.table.sum[j], q, c);
+                unpack_sc(S.u.table.sum[j], q, c);
                 global_add(J.Rp, J.K, (long long)g, q, c);
             }
         }
@@ -853,7 +964,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         const TriR* __restrict__ R = J.recR[s];
         if (cnt[s] <= (unsigned)J.cap) {
             raster_bin<TILE, true>(J.bins[s] + (long long)J.tile * J.cap, cnt[s], R, wave, NW, lane, px0, py0,
-                                   S.key[s], L);
+                                   S.key[s], L, nullptr);
         } else {
             for (int t = wave; t < sc.n_tris; t += NW) {
                 TriR r = gload(&R[t]);

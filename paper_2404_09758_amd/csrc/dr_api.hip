@@ -105,7 +105,7 @@ struct dr_ctx {
     long long* R = nullptr;
     long long R_pairs = 0;
     uint32_t* bits = nullptr;
-    long long bits_pairs = 0;
+    long long bits_words = 0;
     long long* qtot = nullptr;
     long long qtot_pairs = 0;
     double* partials = nullptr;
@@ -464,8 +464,10 @@ extern "C" int64_t dr_group_count(const dr_ctx* c) { return c ? c->sc.G : -1; }
 
 // -------------------------------------------------------------- signs --
 
+// Sign bits of `pairs` pairs, plus a spare word that the texture sampling
+// may read past the last pair's last word.
 static dr_status ensure_bits(dr_ctx* c, long long pairs) {
-    return grow(c, &c->bits, &c->bits_pairs, pairs, (size_t)c->sc.words * sizeof(uint32_t), false);
+    return grow(c, &c->bits, &c->bits_words, pairs * c->sc.words + 1, sizeof(uint32_t), false);
 }
 
 extern "C" dr_status dr_signs(dr_ctx* c, uint64_t seed, uint32_t step, uint32_t pair, uint32_t scene,
@@ -1161,7 +1163,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     BItem* dit = nullptr;
     float *dbc1 = nullptr, *dbc2 = nullptr;
     unsigned* dstep = nullptr;
-    if ((st = balloc(b, &bits, (size_t)bits_total, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
+    if ((st = balloc(b, &bits, (size_t)bits_total + 1, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
         (st = balloc(b, &A.recR, (size_t)rec, false)) || (st = balloc(b, &A.recS, (size_t)rec, false)) ||
         (st = balloc(b, &A.counts, (size_t)cnt, true)) || (st = balloc(b, &A.bins, (size_t)bin, false)) ||
         (st = balloc(b, &dsc, hs.size(), false)) || (st = balloc(b, &dvw, hv.size(), false)) ||

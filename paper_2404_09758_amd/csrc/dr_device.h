@@ -257,14 +257,17 @@ __device__ __forceinline__ T gload(const T* p) {
 // sign words are requested before any is used.  The perturbed value is
 // x + (s_i ? -es : es) with es = +-eps by the render's sign: x - y and
 // x + (-y) are the same IEEE operation, so this equals pval's result.
+// 64-bit word at a 4-byte aligned address (one load of two sign words)
+typedef unsigned long long __attribute__((aligned(4))) drd_u64_a4;
+
 template <int C>
 __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const DRD_GLOBAL uint32_t* pb,
-                                              int words, long long base, int W, float e, float sgn, const Foot& f,
+                                              long long base, int W, float e, float sgn, const Foot& f,
                                               float* out) {
     const DRD_GLOBAL float* tt = th + base;
     const bool pert = pb != nullptr && e != 0.0f;
     const DRD_GLOBAL uint32_t* pw = pb + (base >> 5);
-    unsigned bb = (unsigned)(base & 31), nw = (unsigned)(words - (int)(base >> 5));
+    unsigned bb = (unsigned)(base & 31);
     float es = (sgn > 0.0f) ? e : -e;
     float wx[2] = {1.0f - f.fx, f.fx};
     float acc[C];
@@ -286,18 +289,26 @@ __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const 
             for (int c = 0; c < C; ++c) x[k][c] = tt[(unsigned long long)o[k] + c];
         if (pert) {
             // parameter base + o has its sign at bit (base + o) mod 32 of
-            // word (base + o) / 32; the texel's C bits may run into the next
-            // word (read only while it exists)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                unsigned r = (o[k] & 31u) + bb;
-                unsigned wi = (o[k] >> 5) + (r >> 5);
-                unsigned lo = pw[wi];
-                unsigned win = lo >> (r & 31u);
-                if (C > 1) win = __builtin_amdgcn_alignbit(pw[wi + 1u < nw ? wi + 1u : wi], lo, r & 31u);
-#pragma unroll
-                for (int c = 0; c < C; ++c) x[k][c] = x[k][c] + (((win >> c) & 1u) ? -es : es);
+            // word (base + o) / 32.  One 64-bit read at that word holds the
+            // texel's C bits and, when xb = xa + 1, the next texel's C bits
+            // right after them (at most bit 31 + 2 C < 64); a wrapped xb
+            // reads its own.  The sign buffers carry a spare word at the
+            // end, so the read past a pair's last word stays in bounds (its
+            // bits belong to no parameter of the texel).
+            unsigned r = (o[0] & 31u) + bb;
+            unsigned long long w = *(const DRD_GLOBAL drd_u64_a4*)(pw + (o[0] >> 5) + (r >> 5));
+            unsigned win[2];
+            win[0] = __builtin_amdgcn_alignbit((unsigned)(w >> 32), (unsigned)w, r & 31u);
+            win[1] = win[0] >> C;
+            if (f.xb != f.xa + 1) {
+                unsigned rb = (o[1] & 31u) + bb;
+                unsigned long long wb = *(const DRD_GLOBAL drd_u64_a4*)(pw + (o[1] >> 5) + (rb >> 5));
+                win[1] = __builtin_amdgcn_alignbit((unsigned)(wb >> 32), (unsigned)wb, rb & 31u);
             }
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int c = 0; c < C; ++c) x[k][c] = x[k][c] + (((win[k] >> c) & 1u) ? -es : es);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -319,10 +330,10 @@ __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __rest
     long long base = sc.tex_off[t];
     const DRD_GLOBAL float* gth = (const DRD_GLOBAL float*)th;
     const DRD_GLOBAL uint32_t* gpb = (const DRD_GLOBAL uint32_t*)pb;
-    if (C == 3) sample_texels<3>(gth, gpb, sc.words, base, W, e, sgn, f, out);
-    else if (C == 1) sample_texels<1>(gth, gpb, sc.words, base, W, e, sgn, f, out);
-    else if (C == 4) sample_texels<4>(gth, gpb, sc.words, base, W, e, sgn, f, out);
-    else sample_texels<2>(gth, gpb, sc.words, base, W, e, sgn, f, out);
+    if (C == 3) sample_texels<3>(gth, gpb, base, W, e, sgn, f, out);
+    else if (C == 1) sample_texels<1>(gth, gpb, base, W, e, sgn, f, out);
+    else if (C == 4) sample_texels<4>(gth, gpb, base, W, e, sgn, f, out);
+    else sample_texels<2>(gth, gpb, base, W, e, sgn, f, out);
 }
 
 __device__ __forceinline__ void nrm3(float* x) {

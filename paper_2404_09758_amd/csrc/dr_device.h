@@ -69,15 +69,16 @@ struct DPert {
 };
 
 // Raster half of a triangle record (64 B): snapped vertices in normalised
-// (positive-area) order, the depth plane, flags and the pixel bounding box.
+// (positive-area) order, flags, the depth plane and the pixel bounding box.
+// The first 32 B hold all that the shading reads from it.
 struct __align__(16) TriR {
     int X[3], Y[3];
-    float z0, zx, zy;
     unsigned flags;                      // bit0 valid, bit1+k top-left edge k, bit4 swapped
-    short bx0, by0, bx1, by1;            // inclusive pixel bbox, clamped to the view
-    long long area2;
     float ia;                            // 1 / area2
+    float z0, zx, zy;
+    short bx0, by0, bx1, by1;            // inclusive pixel bbox, clamped to the view
     int pad;
+    long long area2;
 };
 
 // Shading half (64 B): 1/w in normalised order, perturbed world positions
@@ -358,8 +359,18 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
 
 // Face frame of a triangle from its perturbed corners p (original order)
 // and corner UVs: the unit face normal and, for GGX, the tangent frame.
-__device__ __forceinline__ void face_frame(int shading, const float* p, const float* cuv_, TriF& F) {
-    const DRD_GLOBAL float* cuv = (const DRD_GLOBAL float*)cuv_;
+// A triangle's corner UVs (original corner order), read once per shaded
+// pixel and render for both the face frame and the attributes.
+struct CornerUV {
+    float c[6];
+};
+
+__device__ __forceinline__ CornerUV load_cuv(const DScene& sc, unsigned t) {
+    return gload((const CornerUV*)(sc.cuv + 6 * (long long)t));
+}
+
+__device__ __forceinline__ void face_frame(int shading, const float* p, const CornerUV& cu, TriF& F) {
+    const float* cuv = cu.c;
     float e1v[3], e2v[3], nf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) { e1v[c] = p[3 + c] - p[c]; e2v[c] = p[6 + c] - p[c]; }
@@ -389,7 +400,8 @@ struct Attr {
     float pc0, pc1, pc2, iS, u, v;
 };
 
-__device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const TriS& s, int t, int px, int py) {
+__device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const TriS& s, const CornerUV& cu, int px,
+                                          int py) {
     // edge functions as floats; for a TRI_SMALL triangle they fit in 32 bits
     // and convert in one instruction, to the same values
     float f0, f1, f2;
@@ -408,7 +420,7 @@ __device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const
     float S = (pc0 + pc1) + pc2;
     float iS = 1.0f / S;
     bool sw = (r.flags & TRI_SWAPPED) != 0u;
-    const DRD_GLOBAL float* cuv = (const DRD_GLOBAL float*)(sc.cuv + 6 * (long long)t);
+    const float* cuv = cu.c;
     float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];
     float un1 = sw ? cu2 : cu1, vn1 = sw ? cv2 : cv1, un2 = sw ? cu1 : cu2, vn2 = sw ? cv1 : cv2;
     Attr a;
@@ -425,9 +437,10 @@ __device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const
 // three-channel albedo).
 __device__ __forceinline__ void shade_pixel(const DScene& sc, const DView& vw, const float* __restrict__ th,
                                             const uint32_t* __restrict__ pb, const float* eps, float sgn,
-                                            const TriR& r, const TriS& s, const TriF& fr, int t, int px, int py,
+                                            const TriR& r, const TriS& s, const TriF& fr, const CornerUV& cu,
+                                            int px, int py,
                                             float* rgb, float* uvo, Foot& foot0, float& opacity) {
-    Attr a = frag_attr(sc, r, s, t, px, py);
+    Attr a = frag_attr(sc, r, s, cu, px, py);
     float pc0 = a.pc0, pc1 = a.pc1, pc2 = a.pc2, iS = a.iS, u = a.u, v = a.v;
     bool sw = (r.flags & TRI_SWAPPED) != 0u;
     int o1 = sw ? 2 : 1, o2 = sw ? 1 : 2;

@@ -747,11 +747,11 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 TriR r = gload(&J.recR[s][id[s]]);
                 TriS sh = gload(&J.recS[s][id[s]]);
                 TriF fr;
-                if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id[s], fr);
+                CornerUV cu = load_cuv(sc, id[s]);
+                if (sc.shading != 0) face_frame(sc.shading, sh.p, cu, fr);
                 float alpha;
                 Foot f0;
-                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id[s], px, py, rgb[s], uv[s],
-                            f0, alpha);
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, cu, px, py, rgb[s], uv[s], f0, alpha);
             }
         }
         long long pix = (long long)y * vw.W + x;
@@ -1008,10 +1008,11 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                 TriR r = gload(&J.recR[s][id]);
                 TriS sh = gload(&J.recS[s][id]);
                 TriF fr;
-                if (sc.shading != 0) face_frame(sc.shading, sh.p, sc.cuv + 6 * (long long)id, fr);
+                CornerUV cu = load_cuv(sc, id);
+                if (sc.shading != 0) face_frame(sc.shading, sh.p, cu, fr);
                 float c[3], al;
                 Foot f0;
-                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, (int)id, px, py, c, uv, f0, al);
+                shade_pixel(sc, vw, J.theta, J.pb, J.eps, J.sgn[s], r, sh, fr, cu, px, py, c, uv, f0, al);
                 float wt = T * al;
                 rgb[s][0] = rgb[s][0] + wt * c[0];
                 rgb[s][1] = rgb[s][1] + wt * c[1];
@@ -1103,7 +1104,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                 }
                 if (J.any_act && sc.n_cls > 0) {
                     Attr a1 = frag_attr(sc, (s1 ? J.recR[1] : J.recR[0])[id1], (s1 ? J.recS[1] : J.recS[0])[id1],
-                                        (int)id1, px, py);
+                                        load_cuv(sc, id1), px, py);
                     for (int c = 0; c < sc.n_cls; ++c) {
                         if (!J.act_cls[c]) continue;
                         unsigned gs[4];
@@ -1121,7 +1122,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                             if (k2 == ~0ull) continue;
                             unsigned id2 = (unsigned)(k2 & 0xFFFFFFFFull);
                             Attr a2 = frag_attr(sc, (e2 >= L ? J.recR[1] : J.recR[0])[id2],
-                                                (e2 >= L ? J.recS[1] : J.recS[0])[id2], (int)id2, px, py);
+                                                (e2 >= L ? J.recS[1] : J.recS[0])[id2], load_cuv(sc, id2), px, py);
                             unsigned gs2[4];
                             texel_groups(sc, c, a2.u, a2.v, gs2);
 #pragma unroll

@@ -284,10 +284,18 @@ __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const 
         o[0] = ((unsigned)yy * (unsigned)W + (unsigned)f.xa) * C;
         o[1] = ((unsigned)yy * (unsigned)W + (unsigned)f.xb) * C;
         float x[2][C];
+        if (C == 1 && f.xb == f.xa + 1) {
+            // the row's two single-channel texels are adjacent: one 8 B read
+            typedef float __attribute__((ext_vector_type(2), aligned(4))) f2a4;
+            f2a4 v = *(const DRD_GLOBAL f2a4*)(tt + o[0]);
+            x[0][0] = v.x;
+            x[1][0] = v.y;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[k][c] = tt[(unsigned long long)o[k] + c];
+                for (int c = 0; c < C; ++c) x[k][c] = tt[(unsigned long long)o[k] + c];
+        }
         if (pert) {
             // parameter base + o has its sign at bit (base + o) mod 32 of
             // word (base + o) / 32.  One 64-bit read at that word holds the

@@ -277,7 +277,8 @@ def main():
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     launches_per_step = tm["tile_launches"] / args.steps
     alg_bytes_launch = BYTES_PER_PIXEL_ESTIMATE * px_per_step / launches_per_step
-    kernel = f"k_tile_b<{tile}>" if main_mode == "graph" else f"k_tile<{tile},0,false>"
+    # a one-scene batch runs the tile kernel with the scene in its arguments
+    kernel = f"k_tile<{tile},0,false>" if main_mode == "plain" else f"k_tile_b1<{tile}>"
     traffic = measured_traffic(kernel) if args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
     out = {

@@ -963,6 +963,8 @@ struct dr_batch {
     std::string err;
     BatchArgs args{};
     int n_scenes = 0;
+    bool has_one = false;              // one scene: its constants go by value
+    BatchOne one{};
     // device allocations
     std::vector<void*> allocs;
     unsigned long long* stats = nullptr;
@@ -1196,6 +1198,11 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     A.bc2 = dbc2;
     A.step = dstep;
     A.stats = b->stats;
+    if (n_scenes == 1 && hv.size() <= (size_t)DRD_MAX_VIEWS) {
+        b->has_one = true;
+        b->one.sc = hs[0].sc;
+        for (size_t v = 0; v < hv.size(); ++v) b->one.views[v] = hv[v];
+    }
     *out = b;
     return DR_OK;
 }
@@ -1216,7 +1223,8 @@ static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool 
     hipError_t e;
     if ((e = T.run(st, K_SIGNS, [&] { return launch_batch_signs(st, A); })) != hipSuccess) return e;
     if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A); })) != hipSuccess) return e;
-    if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A); })) != hipSuccess) return e;
+    const BatchOne* one = b->has_one ? &b->one : nullptr;
+    if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A, one); })) != hipSuccess) return e;
     if ((e = T.run(st, K_FOLD, [&] { return launch_batch_fold(st, A); })) != hipSuccess) return e;
     if (descend) {
         if ((e = T.run(st, K_STEP, [&] { return launch_batch_step(st, A); })) != hipSuccess) return e;

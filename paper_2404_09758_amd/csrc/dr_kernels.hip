@@ -1439,17 +1439,11 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
 // Raster / shade / scatter of every (scene, pair, view, tile) unit in one
 // launch: one workgroup per unit, units in the XCD-aware order of
 // xcd_tile(), items of the costliest scenes first.
+// One tile unit of the batched launch: the job of item I (scene Sc, whose
+// constants sc and view vw the caller resolves) and the tile body.
 template <int TILE>
-__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b(BatchArgs b) {
-    __shared__ TileShared<TILE, 0> S;
-    long long w = xcd_tile(blockIdx.x, gridDim.x);
-    if (w >= b.total_tiles) return;
-    int it = last_le((const char*)&b.items[0].tile0, sizeof(BItem), b.n_items, w);
-    it = __builtin_amdgcn_readfirstlane(it);
-    const BItem& I = b.items[it];
-    const BScene& Sc = b.scenes[I.scene];
-    const DScene& sc = Sc.sc;
-    const DView& vw = b.views[I.view];
+__device__ __forceinline__ void tile_b_unit(const BatchArgs& b, const BItem& I, const BScene& Sc, const DScene& sc,
+                                            const DView& vw, long long w, TileShared<TILE, 0>& S) {
     int tiles = vw.tiles_x * vw.tiles_y;
     TileJob J;
     J.sc = &sc;
@@ -1482,6 +1476,35 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE 
     J.partial = nullptr;
     J.qtot = nullptr;
     tile_body<TILE, 0>(J, S);
+}
+
+// Item of tile unit w (uniform).
+__device__ __forceinline__ int unit_item(const BatchArgs& b, long long w) {
+    int it = last_le((const char*)&b.items[0].tile0, sizeof(BItem), b.n_items, w);
+    return __builtin_amdgcn_readfirstlane(it);
+}
+
+template <int TILE>
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b(BatchArgs b) {
+    __shared__ TileShared<TILE, 0> S;
+    long long w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= b.total_tiles) return;
+    const BItem& I = b.items[unit_item(b, w)];
+    const BScene& Sc = b.scenes[I.scene];
+    tile_b_unit<TILE>(b, I, Sc, Sc.sc, b.views[I.view], w, S);
+}
+
+// The same launch for a one-scene batch, with the scene's constants and
+// views in the kernel arguments: the body reads them with scalar loads
+// instead of vector loads that compete with the texel reads.
+template <int TILE>
+__global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b1(BatchArgs b, BatchOne one) {
+    __shared__ TileShared<TILE, 0> S;
+    long long w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= b.total_tiles) return;
+    const BItem& I = b.items[unit_item(b, w)];
+    const BScene& Sc = b.scenes[I.scene];
+    tile_b_unit<TILE>(b, I, Sc, one.sc, one.views[I.view], w, S);
 }
 
 // Fold and step over the groups of every scene: each scene starts on a
@@ -1610,12 +1633,18 @@ hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b) {
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one) {
     int tb = (b.tile * b.tile > 256) ? 256 : b.tile * b.tile;
     unsigned grid = (unsigned)b.total_tiles;
-    if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, b);
-    else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, b);
-    else hipLaunchKernelGGL(k_tile_b<32>, dim3(grid), dim3(tb), 0, st, b);
+    if (one) {
+        if (b.tile == 8) hipLaunchKernelGGL(k_tile_b1<8>, dim3(grid), dim3(tb), 0, st, b, *one);
+        else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b1<16>, dim3(grid), dim3(tb), 0, st, b, *one);
+        else hipLaunchKernelGGL(k_tile_b1<32>, dim3(grid), dim3(tb), 0, st, b, *one);
+    } else {
+        if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, b);
+        else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, b);
+        else hipLaunchKernelGGL(k_tile_b<32>, dim3(grid), dim3(tb), 0, st, b);
+    }
     return hipGetLastError();
 }
 

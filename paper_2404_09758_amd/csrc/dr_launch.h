@@ -177,7 +177,16 @@ hipError_t launch_step(hipStream_t st, const StepArgs& a);
 
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b);
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b);
+// A one-scene batch's scene constants and views, passed to the tile launch
+// by value.
+struct BatchOne {
+    DScene sc;
+    DView views[DRD_MAX_VIEWS];
+};
+
+// one: non-null for a one-scene batch (the batch's view table is then the
+// scene's views).
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one);
 hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b);

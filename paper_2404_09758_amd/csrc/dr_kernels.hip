@@ -552,7 +552,9 @@ template <int LOG2T>
 __device__ __forceinline__ void table_add(GroupTable<LOG2T>& tb, long long* __restrict__ Rp,
                                           unsigned* __restrict__ K, unsigned g, long long q, unsigned c) {
     constexpr unsigned MASK = (1u << LOG2T) - 1u;
-    unsigned h = (g * 2654435761u) >> (32 - LOG2T);
+    // multiplicative hash in 24-bit multiplies (full rate; the 32-bit one is
+    // quarter rate), the high byte folded in first
+    unsigned h = (__umul24(g ^ (g >> 24), 0x9E3779u) >> (24 - LOG2T)) & MASK;
     for (int probe = 0; probe < HASH_PROBES; ++probe) {
         unsigned k = __hip_atomic_load(&tb.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == HASH_EMPTY) k = atomicCAS(&tb.key[h], HASH_EMPTY, g);
@@ -675,6 +677,7 @@ struct TileShared {
     } u;
     double red[MODE == 2 ? TB : 1];
     long long qred[MODE == 3 ? TB : 1];
+    unsigned nfl;                        // occupied table slots (flush)
 };
 
 template <int TILE, int MODE>
@@ -721,6 +724,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     }
     if constexpr (MODE == 0) {
         // the stages are done with: the group table takes their place
+        if (tid == 0) S.nfl = 0u;
         for (int j = tid; j < TSIZE; j += TB) {
             S.u.table.key[j] = HASH_EMPTY;
             S.u.table.sum[j] = 0ull;
@@ -877,13 +881,37 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     }
     if constexpr (MODE == 0) {
         __syncthreads();
-        for (int j = tid; j < TSIZE; j += TB) {
-            unsigned g = S.u.table.key[j];
-            if (g != HASH_EMPTY) {
+        if constexpr (TILE >= 16) {
+            // occupied slots first gathered into a dense list (in the key
+            // buffers, free by now and large enough from 16-pixel tiles
+            // on), so the global atomics go out in full waves
+            unsigned* list = reinterpret_cast<unsigned*>(&S.key[0][0]);
+            for (int j = tid; j < TSIZE; j += TB) {
+                bool occ = S.u.table.key[j] != HASH_EMPTY;
+                unsigned long long m = __ballot(occ);
+                unsigned base = 0;
+                if (lane == 0 && m) base = atomicAdd(&S.nfl, (unsigned)__popcll(m));
+                base = __shfl(base, 0);
+                if (occ) list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = (unsigned)j;
+            }
+            __syncthreads();
+            unsigned n = S.nfl;
+            for (unsigned i = (unsigned)tid; i < n; i += TB) {
+                unsigned j = list[i];
                 long long q;
                 unsigned c;
                 unpack_sc(S.u.table.sum[j], q, c);
-                global_add(J.Rp, J.K, (long long)g, q, c);
+                global_add(J.Rp, J.K, (long long)S.u.table.key[j], q, c);
+            }
+        } else {
+            for (int j = tid; j < TSIZE; j += TB) {
+                unsigned g = S.u.table.key[j];
+                if (g != HASH_EMPTY) {
+                    long long q;
+                    unsigned c;
+                    unpack_sc(S.u.table.sum[j], q, c);
+                    global_add(J.Rp, J.K, (long long)g, q, c);
+                }
             }
         }
     }

@@ -565,3 +565,39 @@ def test_new_forms_edge_cases():
         assert np.array_equal(host(Qg), Qo) and np.array_equal(host(Kg).view(np.uint32), Ko)
         with pytest.raises(api.DRError):
             batch.Batch([sc2], 1, DEV, tile_px=8, targets=[[dev(t1)]])
+
+
+@pytest.mark.parametrize("shading,shapes", [
+    (S.SHADING_UNLIT, [(6, 10, 3)]),                         # d = 12 + 180 = 192
+    (S.SHADING_GGX, [(4, 11, 3), (4, 11, 3), (4, 11, 1)]),   # d = 12 + 308 = 320
+])
+def test_texel_signs_at_the_end_of_the_parameter_vector(shading, shapes):
+    """d is a multiple of 32, so the last texels' sign bits sit at the top of
+    each pair's last sign word and a texel row's 64-bit sign read runs past
+    it (into the next pair's words, or the buffer's spare word after the
+    last pair); the quad's right edge also samples the wrapped texel column.
+    Plain and one-scene batched paths vs the oracle."""
+    d = 12 + sum(h * w * c for h, w, c in shapes)
+    assert d % 32 == 0
+    rng = np.random.default_rng(11)
+    q = H.quad_scene(np.zeros(shapes[0], np.float32), extent=0.9)
+    tex = [rng.uniform(0.1, 0.9, sh).astype(np.float32) for sh in shapes]
+    ttex = [rng.uniform(0.1, 0.9, sh).astype(np.float32) for sh in shapes]
+    views = [S.look_at_view(40, 36, 0.0, 0.0), S.look_at_view(33, 40, 20.0, 10.0)]
+    eps = [0.01] + [1.0 / 255.0] * len(shapes)
+    sc = S.Scene("quad", q.tri, q.corner_uv, q.pos, tex, q.pos.copy(), ttex, views, shading=shading,
+                 eps=eps, lr=eps, n_pairs=3)
+    assert sc.n_params == d
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    seed, step, pairs = 77, 2, 3
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, seed, step, pairs, sc.eps)
+    h, w, _ = shapes[-1]
+    assert np.count_nonzero(Ko[-h * w:]) > 0            # the last texels are sampled
+    ctx = api.Context(sc, DEV, tuning=(8, 64, 0))
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], seed, step, pairs, sc.eps)
+    assert np.array_equal(host(K).view(np.uint32), Ko) and np.array_equal(host(Q), Qo)
+    bt = batch.Batch([sc], pairs, DEV, tile_px=8, seed=seed, first_step=step, targets=[[dev(t) for t in tg]])
+    bt.estimate()
+    assert np.array_equal(host(bt.K[0]).view(np.uint32), Ko) and np.array_equal(host(bt.Q[0]), Qo)

@@ -289,6 +289,21 @@ __device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, i
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts
+// by 1, 2, 4 and 8 within each row of 16 lanes (lanes shifted in from
+// outside the row add 0), then row 0's total to row 1 and row 2's to row 3
+// (row_bcast:15), then row 1's running total to rows 2 and 3 (row_bcast:31).
+// Must be called by every lane of the wave.
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);     // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);     // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);     // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);     // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);     // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);     // row_bcast:31
+    return v;
+}
+
 // Per-wave LDS staging of a batch of small triangles for the packed raster
 // (80 B each): edge k as an integer plane over the triangle's clipped
 // bounding box, e_k(dx, dy) = a_k dx + b_k dy + c_k at pixel (x0 + dx,
@@ -410,21 +425,18 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
             c = bw * (y1 - y0 + 1);
         }
     }
-    int P = c;                                          // inclusive prefix sums over the lanes
-    int T = (c + 63) >> 6;                              // passes of the per-triangle loop
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int v = __shfl_up(P, off), w = __shfl_up(T, off);
-        if (lane >= off) { P += v; T += w; }
-    }
-    int N = __shfl(P, 63);
-    int passes_tri = __shfl(T, 63);
-    int passes_packed = (N + 63) >> 6;
-    if (stage != nullptr && passes_packed <= passes_tri &&
-        __ballot(c > 0 && !(r.flags & TRI_SMALL)) == 0ull) {
+    int P = wave_inclusive_sum(c);                      // prefix sums of the pixel counts
+    int N = __builtin_amdgcn_readlane(P, 63);
+    // Packed, ceil(sum c / 64) passes, never takes more passes than one
+    // triangle at a time, sum ceil(c / 64): the staged form is taken
+    // whenever it applies.
+    if (stage != nullptr && __ballot(c > 0 && !(r.flags & TRI_SMALL)) == 0ull) {
         raster_staged<TILE, DEEP>(stage, r, mine, c, x0, y0, bw, P - c, N, px0, py0, lane, key, L);
         return;
     }
+    int T = wave_inclusive_sum((c + 63) >> 6);          // passes of the per-triangle loop
+    int passes_tri = __builtin_amdgcn_readlane(T, 63);
+    int passes_packed = (N + 63) >> 6;
     if (4 * passes_packed >= 3 * passes_tri) {
         // one triangle at a time, its record read from the lane that holds it
         const int* mw = reinterpret_cast<const int*>(&r);

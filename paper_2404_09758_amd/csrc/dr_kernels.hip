@@ -18,8 +18,9 @@
 //   step       decode, per-parameter average, Adam / SGD    (shader D)
 // An "item" is one (pair, view) of a scene.  The single-scene kernels take
 // their descriptors as kernel arguments; the batch kernels read them from
-// device memory and cover many scenes per launch.  Both share the bodies
-// below, so they compute the same bits.
+// device memory and cover many scenes per launch (the tile launch of a
+// one-scene batch takes the scene and its views as kernel arguments too).
+// All share the bodies below, so they compute the same bits.
 #include <type_traits>
 
 #include "dr_launch.h"

@@ -1225,6 +1225,11 @@ static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool 
     if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A); })) != hipSuccess) return e;
     const BatchOne* one = b->has_one ? &b->one : nullptr;
     if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A, one); })) != hipSuccess) return e;
+    if (descend && A.n_pairs <= 8) {
+        // the fold's sums go straight into the update (timed as the step)
+        if ((e = T.run(st, K_STEP, [&] { return launch_batch_fold_step(st, A); })) != hipSuccess) return e;
+        return launch_batch_end(st, A);
+    }
     if ((e = T.run(st, K_FOLD, [&] { return launch_batch_fold(st, A); })) != hipSuccess) return e;
     if (descend) {
         if ((e = T.run(st, K_STEP, [&] { return launch_batch_step(st, A); })) != hipSuccess) return e;

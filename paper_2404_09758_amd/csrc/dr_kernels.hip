@@ -1574,6 +1574,82 @@ __global__ void __launch_bounds__(256) k_step_b(BatchArgs b) {
                S.K, nullptr, b.stats);
 }
 
+// Fold and step fused, for a descent over at most 8 pairs: each group's
+// per-pair sums are read once and every parameter of the group goes from
+// its sum straight to the update, so the fixed-point sums Q are not written
+// and read back in between.  Q_i + sum_n s_i^(n) R_g^(n) is the value the
+// fold would leave in Q; it is used as step_group uses Q, and Q, R and K are
+// left zero as the two kernels leave them.
+__device__ __forceinline__ void fold_step_group(const DScene& sc, long long g, long long* __restrict__ R,
+                                                const uint32_t* __restrict__ bits, int n_pairs, const float* eps,
+                                                const float* lr, const OptimConst& oc, float bc1, float bc2,
+                                                float* __restrict__ theta, float* __restrict__ m,
+                                                float* __restrict__ v, long long* __restrict__ Q,
+                                                unsigned* __restrict__ K, unsigned long long* __restrict__ stats) {
+    long long r[8];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        r[j] = (j < n_pairs) ? R[(long long)j * sc.G + g] : 0;
+        any = any || r[j] != 0;
+    }
+    unsigned kc = K[g];
+    double D = (oc.averaging == 0) ? (double)kc : (double)n_pairs;
+    for_params(sc, g, [&](long long i, int b) {
+        float e = eps[b];
+        long long q0 = Q[i];
+        long long acc = 0;
+        if (any && e != 0.0f) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (r[j] == 0) continue;
+                acc += (sign_of(bits + (long long)j * sc.words, i) > 0) ? r[j] : -r[j];
+            }
+        }
+        long long qv = q0 + acc;
+        float gi = 0.0f;
+        if (e != 0.0f && D != 0.0)
+            gi = (float)(((double)qv * (1.0 / 4294967296.0)) / (2.0 * (double)e * D));
+        if (q0 != 0) Q[i] = 0;
+        if (e == 0.0f) return;
+        if (oc.averaging == 0 && kc == 0u) return;
+        if (!(fabsf(gi) <= 3.402823466e38f)) {
+            atomicAdd(&stats[ST_NONFINITE], 1ull);
+            return;
+        }
+        float l = lr[b];
+        if (oc.kind == 1) {
+            theta[i] = theta[i] - l * gi;
+        } else {
+            float mi = oc.b1 * m[i] + oc.omb1 * gi;
+            float vi = oc.b2 * v[i] + oc.omb2 * (gi * gi);
+            m[i] = mi;
+            v[i] = vi;
+            float mh = mi / bc1;
+            float vh = vi / bc2;
+            theta[i] = theta[i] - l * (mh / (sqrtf(vh) + oc.eps_hat));
+        }
+    });
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (r[j] != 0) R[(long long)j * sc.G + g] = 0;
+    K[g] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_fold_step_b(BatchArgs b) {
+    long long blk = blockIdx.x;
+    int si = last_le((const char*)&b.scenes[0].group_blk0, sizeof(BScene), b.n_scenes, blk);
+    si = __builtin_amdgcn_readfirstlane(si);
+    const BScene& S = b.scenes[si];
+    long long g = (blk - S.group_blk0) * 256 + threadIdx.x;
+    if (g >= S.sc.G) return;
+    unsigned t = *b.step;
+    if (t < 1u) t = 1u;                      // Adam steps count from 1
+    int ti = (int)min(t, (unsigned)b.n_bc) - 1;
+    fold_step_group(S.sc, g, S.R, S.bits, b.n_pairs, S.eps, S.lr, b.oc, b.bc1[ti], b.bc2[ti], (float*)S.theta,
+                    S.m, S.v, S.Q, S.K, b.stats);
+}
+
 // --------------------------------------------------------- launchers --
 
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
@@ -1691,6 +1767,11 @@ hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne*
 
 hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b) {
     hipLaunchKernelGGL(k_fold_b, dim3((unsigned)b.group_blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fold_step(hipStream_t st, const BatchArgs& b) {
+    hipLaunchKernelGGL(k_fold_step_b, dim3((unsigned)b.group_blocks), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

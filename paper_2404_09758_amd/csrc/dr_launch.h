@@ -189,4 +189,6 @@ struct BatchOne {
 hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one);
 hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b);
+// fold and step in one launch (at most 8 pairs)
+hipError_t launch_batch_fold_step(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_end(hipStream_t st, const BatchArgs& b);

@@ -143,3 +143,32 @@ def test_paper_step_in_the_bench_launch_shape_matches_oracle():
     o.step(th_o, m_o, v_o, step, Qo2, Ko2, sc.eps, sc.n_pairs, kind=S.OPT_ADAM, averaging=S.AVG_COUNT, lr=sc.lr)
     assert np.array_equal(host(bt.theta[0]), th_o)
     assert np.array_equal(host(bt.m[0]), m_o) and np.array_equal(host(bt.v[0]), v_o)
+
+
+@pytest.mark.parametrize("pairs", [2, 11])
+def test_batch_step_after_estimate_matches_plain(pairs):
+    """A descent after an estimate that left sums in Q: the fused fold and
+    step (at most 8 pairs) adds its sums to them, more pairs take the
+    separate fold and step; both equal the plain path bit for bit."""
+    scs = make_scenes()
+    seed, t = 5, 2
+    bt = batch.Batch(scs, pairs, DEV, tile_px=16, seed=seed, first_step=t)
+    ctxs, th, m, v = [], [], [], []
+    for b, sc in enumerate(scs):
+        c = api.Context(sc, DEV, tuning=(16, 256, 1))
+        c.set_scene_index(b)
+        ctxs.append(c)
+        th.append(bt.theta[b].clone())
+        m.append(bt.m[b].clone())
+        v.append(bt.v[b].clone())
+    bt.estimate()                      # sums of step t into Q and K; the step stays t
+    bt.step(use_graph=False)           # the same sums again, then the descent of step t
+    for b, sc in enumerate(scs):
+        Q, K = ctxs[b].estimate_grad(th[b], sc.views, bt.targets[b], seed, t, pairs, sc.eps)
+        ctxs[b].estimate_grad(th[b], sc.views, bt.targets[b], seed, t, pairs, sc.eps, Q=Q, K=K)
+        ctxs[b].step(th[b], m[b], v[b], t, Q, K, sc.eps, pairs, kind=api.ADAM, averaging=api.AVG_COUNT, lr=sc.lr)
+    torch.cuda.synchronize()
+    for b in range(len(scs)):
+        assert torch.equal(bt.theta[b], th[b]) and torch.equal(bt.m[b], m[b]) and torch.equal(bt.v[b], v[b])
+        assert not bt.Q[b].any() and not bt.K[b].any()
+    assert bt.get_step() == t + 1

@@ -336,9 +336,10 @@ static_assert(sizeof(PTri) == 80, "PTri layout");
 // is then the number of triangles begun up to its slot (a ballot and a
 // lane-masked bit count) -- one LDS read of the staged record instead of a
 // binary search and a shuffle per field.  Edge values are exact: for a
-// TRI_SMALL triangle every term is below 2^30 in magnitude, so the 32-bit
-// sums equal the 64-bit ones, and e > 0 || (e == 0 && top-left) is
-// e + [top-left] > 0.
+// TRI_SMALL triangle both products of an edge function are below 2^30 in
+// magnitude at every pixel of the box, so the edge value (and its value
+// plus 1) fits in 32 bits and the wrapped 32-bit sums a dx + b dy + c equal
+// it; e > 0 || (e == 0 && top-left) is e + [top-left] > 0.
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, unsigned t, int c, int x0, int y0,
                                               int bw, int pex, int N, int px0, int py0, int lane,

@@ -211,6 +211,56 @@ def test_raster_matches_float64_point_in_triangle(oracle_lib):
     assert np.array_equal(ids.astype(np.int64)[ok], ref[ok])
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sloped_intersecting_triangles_match_float64_depth(seed, oracle_lib):
+    """Interpenetrating triangles whose depth varies along x and along y:
+    each pixel shows the triangle whose plane is nearest at the pixel centre,
+    computed in float64 from the unsnapped vertices (barycentric depth in
+    screen space, exact under the identity projection).  Pixels within
+    1/64 px of an edge or where the two nearest planes are within 2e-4 in
+    depth (vertex snapping, fp32 plane slopes) are left out."""
+    rng = np.random.default_rng(100 + seed)
+    W, Hh = 56, 48
+    n = 12
+    pos = rng.uniform(-1.0, 1.0, (3 * n, 3)).astype(np.float32)
+    pos[:, 2] = rng.uniform(-0.85, 0.85, 3 * n).astype(np.float32)     # tilted in x and y
+    tri = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    sc = H.SimpleScene(tri, np.zeros((n, 3, 2), np.float32), pos, [np.full((2, 2, 3), 0.5)])
+    _, ids, _ = oracle.Oracle(sc).render(sc.flat(), H.ndc_view(W, Hh))
+    p64 = pos.astype(np.float64)
+    sx = (p64[:, 0] * 0.5 + 0.5) * W
+    sy = (0.5 - p64[:, 1] * 0.5) * Hh
+    sz = p64[:, 2] * 0.5 + 0.5
+    px, py = np.meshgrid(np.arange(W) + 0.5, np.arange(Hh) + 0.5)
+    depths = np.full((n, Hh, W), np.inf)
+    near_edge = np.zeros((Hh, W), bool)
+    for t in range(n):
+        X, Y, Z = sx[3 * t:3 * t + 3], sy[3 * t:3 * t + 3], sz[3 * t:3 * t + 3]
+        area = (X[1] - X[0]) * (Y[2] - Y[0]) - (Y[1] - Y[0]) * (X[2] - X[0])
+        if abs(area) < 1e-6:
+            continue
+        b = []
+        inside = np.ones((Hh, W), bool)
+        for k in range(3):
+            i, j = (k + 1) % 3, (k + 2) % 3
+            e = (X[j] - X[i]) * (py - Y[i]) - (Y[j] - Y[i]) * (px - X[i])
+            b.append(e / area)
+            inside &= e / area > 0
+            near_edge |= np.abs(e) / math.hypot(X[j] - X[i], Y[j] - Y[i]) < 1.0 / 64
+        z = b[0] * Z[0] + b[1] * Z[1] + b[2] * Z[2]
+        depths[t][inside] = z[inside]
+    order = np.sort(depths, axis=0)
+    ref = np.where(np.isfinite(order[0]), np.argmin(depths, axis=0), oracle.BG_ID)
+    with np.errstate(invalid="ignore"):
+        close = np.isfinite(order[1]) & (order[1] - order[0] < 2e-4)
+    ok = ~near_edge & ~close
+    # many pixels are decided by depth between overlapping, differently tilted planes
+    overlapped = ok & np.isfinite(order[1])
+    assert overlapped.sum() > 300
+    assert ok.mean() > 0.6
+    assert np.array_equal(ids.astype(np.int64)[ok], ref[ok])
+
+
 # ---------------------------------------------- attributes and sampling ---
 
 def _wrap_pad(tex):
@@ -339,6 +389,64 @@ def test_ggx_closed_form_at_centre_pixel(rough, light_deg, tilt_deg, oracle_lib)
     ref = [_ggx_ref(float(a), rough, max(n @ L, 0), max(n @ v, 0), max(n @ h, 0), max(v @ h, 0), 1.0, 0.03)
            for a in albedo]
     assert np.allclose(rgb[7, 7], ref, rtol=2e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("mirrored", [False, True])
+@pytest.mark.parametrize("rough,light,tilt_deg", [(0.5, (0.0, 0.5, 1.0), 30.0), (0.7, (0.3, -0.6, 1.0), -35.0),
+                                                  (0.4, (-0.2, 0.8, 1.0), 20.0)])
+def test_ggx_normal_map_tilt_along_v(mirrored, rough, light, tilt_deg, oracle_lib):
+    """The normal map's second (green) channel tilts the normal along the
+    face's bitangent.  Convention (the paper names a tangent-space normal map
+    but no frame): T is the unit direction of increasing u in the face plane,
+    found here by solving the corner UVs' linear map in float64, and
+    B = N x T for either winding of the UV map (mirrored: v runs the other
+    way on screen).  Checked at the centre pixel, where the view vector is
+    +z exactly, under lights with a component along B."""
+    pos, tri, uv, view = _facing_triangle()
+    if mirrored:
+        uv = uv.copy()
+        uv[..., 1] = 1.0 - uv[..., 1]
+    albedo = np.array([0.6, 0.4, 0.2], np.float32)
+    L = np.array(light, np.float64)
+    L = L / np.linalg.norm(L)
+    ta = math.radians(tilt_deg)
+    nmv = np.array([0.5, 0.5 + 0.5 * math.sin(ta), 0.5 + 0.5 * math.cos(ta)], np.float32)
+    tex = [np.tile(albedo, (4, 4, 1)), np.tile(nmv, (4, 4, 1)), np.full((4, 4, 1), rough, np.float32)]
+    sc = H.SimpleScene(tri, uv, pos, tex, shading=S.SHADING_GGX, light_dir=L.astype(np.float32),
+                       light_rgb=np.array([1.0, 1.0, 1.0], np.float32), ambient=0.03)
+    rgb, ids, _ = oracle.Oracle(sc).render(sc.flat(), view)
+    assert ids[7, 7] == 0
+    P = pos.astype(np.float64)
+    c = uv[0].astype(np.float64)
+    e1, e2 = P[1] - P[0], P[2] - P[0]
+    N = np.cross(e1, e2)
+    N /= np.linalg.norm(N)
+    # [e1; e2] = [[du1, dv1], [du2, dv2]] [dP/du; dP/dv]
+    J = np.array([[c[1, 0] - c[0, 0], c[1, 1] - c[0, 1]], [c[2, 0] - c[0, 0], c[2, 1] - c[0, 1]]])
+    dPdu, dPdv = np.linalg.solve(J, np.stack([e1, e2]))
+    T = dPdu - N * (N @ dPdu)
+    T /= np.linalg.norm(T)
+    B = np.cross(N, T)
+    # the two maps have opposite UV orientation (r = du1 dv2 - du2 dv1 < 0
+    # for the facing triangle's own map, > 0 mirrored); B follows N x T in
+    # both, so it runs against dP/dv in one and along it in the other
+    r = J[0, 0] * J[1, 1] - J[1, 0] * J[0, 1]
+    assert (r > 0) == mirrored
+    assert (B @ dPdv > 0) == mirrored
+    tn = 2.0 * nmv.astype(np.float64) - 1.0
+    n = tn[0] * T + tn[1] * B + tn[2] * N
+    n /= np.linalg.norm(n)
+    v = np.array([0, 0, 1.0])
+    h = (L + v) / np.linalg.norm(L + v)
+    ref = [_ggx_ref(float(a), rough, max(n @ L, 0), max(n @ v, 0), max(n @ h, 0), max(v @ h, 0), 1.0, 0.03)
+           for a in albedo]
+    assert np.allclose(rgb[7, 7], ref, rtol=2e-5, atol=1e-6)
+    # the opposite handedness gives a visibly different colour here
+    n2 = tn[0] * T - tn[1] * B + tn[2] * N
+    n2 /= np.linalg.norm(n2)
+    h2 = [_ggx_ref(float(a), rough, max(n2 @ L, 0), max(n2 @ v, 0), max(n2 @ h, 0), max(v @ h, 0), 1.0, 0.03)
+          for a in albedo]
+    assert np.abs(np.array(h2) - np.array(ref)).max() > 1e-3
 
 
 # -------------------------------------------------- estimator: closed form ---

@@ -328,6 +328,17 @@ struct RasterStage {
     int mark[64];
 };
 
+// Lanes of one wave exchange data through the wave's stage: a release fence
+// before the wave barrier and an acquire fence after it make each lane's LDS
+// stores visible to the other lanes' later loads (the barrier itself
+// declares no memory effects, so without the fences the compiler could
+// forward a lane's own store to its load past the other lanes' writes).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 static_assert(sizeof(PTri) == 80, "PTri layout");
 
 // Packed raster of a batch whose triangles are all TRI_SMALL, through the
@@ -368,13 +379,13 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
         q.pad = 0;
         st->tri[rank] = q;
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     int base = 0;                                       // triangles begun before this pass
     for (int s0 = 0; s0 < N; s0 += 64) {
         st->mark[lane] = 0;
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         if (c > 0 && pex >= s0 && pex < s0 + 64) st->mark[pex - s0] = 1;
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         int f = st->mark[lane];
         unsigned long long M = __ballot(f != 0);
         int rr = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(M >> 32),
@@ -396,7 +407,7 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
                                  ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
 }
 

@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--config", default="paper",
                     choices=["paper", "mid", "tiny", "batch64", "soup", "layers", "subdiv"])
     ap.add_argument("--soup-steps", type=int, default=100, help="Adam steps per run of the soup config")
-    ap.add_argument("--cpu-items", type=int, default=8, help="oracle sample: (pair, view) items")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle: whole steps timed per core count")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="both", choices=["both", "graph", "batched", "plain"])
     ap.add_argument("--probe-copy-mib", type=int, default=0,
@@ -128,34 +128,100 @@ def run_mode(ctx, sc, th, m, v, tg, eps, steps, warmup, tuning, api, torch):
             "contributions_per_step": contributions}
 
 
-def cpu_baseline(sc, n_items):
+def host_cpu():
+    """Model name and usable core count of the host that runs the oracle."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
+
+
+def cpu_baseline(sc, reps=3, threads=None):
+    """The oracle timed on whole optimisation steps: the estimate over every
+    (pair, view) item plus the Adam step, on one host core and on all usable
+    host cores (a thread pool over the items; the oracle releases the
+    interpreter lock inside each call).  Each item's integer sums go to its
+    thread's own accumulators, added at the end, so Q and K are bit-identical
+    to the single-threaded step (checked).  Median of `reps` steps per core
+    count.  Signs, renders, differences, scatter and descent all run in the
+    oracle; the targets are inputs, rendered before timing."""
+    import concurrent.futures as cf
+    import statistics
+
     import numpy as np
 
     import oracle
+    model, usable = host_cpu()
+    if threads is None:
+        # the box's CPU share for one GPU is 16 cores, whatever the machine has
+        threads = max(1, min(usable, int(os.environ.get("OMP_NUM_THREADS", "16")), 16))
     o = oracle.Oracle(sc)
     theta = sc.flat_params()
     views = sc.views
-    items = [(n, v) for n in range(sc.n_pairs) for v in range(len(views))][:n_items]
+    items = [(n, v) for n in range(sc.n_pairs) for v in range(len(views))]
     targets = [o.render(sc.flat_params(True), vw)[0] for vw in views]
-    t0 = time.perf_counter()
-    Q = np.zeros(o.d, np.int64)
-    K = np.zeros(o.G, np.uint32)
-    for (n, v) in items:
-        # the oracle's estimate of one (pair, view) item: pair n via a sign table
+
+    def item(n, v, Q, K):
         s = oracle.signs(sc.seed, 1, n, 0, o.d)[None]
         o.estimate(theta, [views[v]], [targets[v]], sc.seed, 1, 1, sc.eps, signs_=s, Q=Q, K=K)
-    t_items = time.perf_counter() - t0
-    th = theta.copy()
-    m = np.zeros(o.d, np.float32)
-    vv = np.zeros(o.d, np.float32)
-    t1 = time.perf_counter()
-    o.step(th, m, vv, 1, Q, K, sc.eps, sc.n_pairs, kind=0, averaging=0, lr=sc.lr)
-    t_step = time.perf_counter() - t1
-    total_items = sc.n_pairs * len(views)
-    sec_per_step = t_items / len(items) * total_items + t_step
-    return {"value": 1.0 / sec_per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(items)} of {total_items} (pair, view) items of one step plus one full Adam "
-                      f"step, single-threaded, extrapolated to a whole step ({sec_per_step:.1f} s/step)"}
+
+    def one_step(nthr):
+        t0 = time.perf_counter()
+        if nthr == 1:
+            Q = np.zeros(o.d, np.int64)
+            K = np.zeros(o.G, np.uint32)
+            for (n, v) in items:
+                item(n, v, Q, K)
+        else:
+            accs = [(np.zeros(o.d, np.int64), np.zeros(o.G, np.uint32)) for _ in range(nthr)]
+
+            def work(w):
+                for (n, v) in items[w::nthr]:
+                    item(n, v, accs[w][0], accs[w][1])
+
+            with cf.ThreadPoolExecutor(nthr) as ex:
+                list(ex.map(work, range(nthr)))
+            Q, K = accs[0]
+            for q, k in accs[1:]:
+                Q += q
+                K += k
+        th = theta.copy()
+        m = np.zeros(o.d, np.float32)
+        vv = np.zeros(o.d, np.float32)
+        o.step(th, m, vv, 1, Q.copy(), K.copy(), sc.eps, sc.n_pairs, kind=0, averaging=0, lr=sc.lr)
+        return time.perf_counter() - t0, Q, K, th
+
+    legs = {}
+    ref = None
+    for nthr in sorted({1, threads}):
+        runs = []
+        for _ in range(reps):
+            dt, Q, K, th = one_step(nthr)
+            runs.append(dt)
+            if ref is None:
+                ref = (Q, K, th)
+            elif not (np.array_equal(Q, ref[0]) and np.array_equal(K, ref[1]) and np.array_equal(th, ref[2])):
+                raise RuntimeError("oracle step differs between core counts")
+        med = statistics.median(runs)
+        legs[nthr] = {"value": 1.0 / med, "unit": "steps/s", "cores": nthr, "s_per_step_runs": runs}
+        progress(f"cpu baseline: {nthr} thread(s), {med:.2f} s/step (median of {reps})")
+    top = legs[threads]
+    px = sc.n_pairs * sum(v.width * v.height for v in views)
+    return {"value": top["value"], "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole steps: all {len(items)} (pair, view) items of an estimate plus the Adam step; "
+                      f"median of {reps} per core count; threads over items, integer sums bit-identical "
+                      f"to one thread",
+            "pixel_estimates_per_s": px * top["value"],
+            "single_core": legs[1], "all_cores": top, "nproc": usable, "cpu_model": model}
 
 
 def run_graph_mode(sc_list, tg_list, steps, warmup, api, batch_mod, torch, dev, tile=16, caps=None):
@@ -327,7 +393,7 @@ def main():
         out["copy_probe_bytes"] = 4 * n
     if not args.no_cpu:
         progress("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_items)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_reps)
     print(json.dumps(out), flush=True)
 
 
@@ -450,7 +516,7 @@ def main_layers(args, torch, api, autotune, scenes, dev):
                             "kernel_avg_ms": tile_ms},
                "kernels_ms_per_step": {k[:-3]: tm[k] / args.steps for k in tm if k.endswith("_ms")}}
         if not args.no_cpu:
-            cb = cpu_baseline(sc, 1)
+            cb = cpu_baseline(sc, args.cpu_reps)
             row["cpu_baseline"] = cb
         rows.append(row)
         progress(f"layers {layers}: {row['steps_per_s']:.1f} steps/s")

@@ -262,8 +262,10 @@ def run_graph_mode(sc_list, tg_list, steps, warmup, api, batch_mod, torch, dev, 
             "stats": st, "batch": bt}
 
 
-def run_sequential_plain(sc_list, tg_list, steps, warmup, api, torch, dev, tile=16, caps=None):
-    """Each scene stepped on its own with one raster launch per item."""
+def run_sequential_plain(sc_list, tg_list, steps, warmup, api, torch, dev, tile=16, caps=None, seed=0):
+    """Each scene stepped on its own with one raster launch per item.  The
+    signs are drawn as in the batch: one seed, the scene's index in the
+    Philox counter."""
     ctxs, th, m, v = [], [], [], []
     for b, sc in enumerate(sc_list):
         c = api.Context(sc, dev, tuning=(tile, 256 if caps is None else caps[b], 1))
@@ -278,7 +280,7 @@ def run_sequential_plain(sc_list, tg_list, steps, warmup, api, torch, dev, tile=
         nonlocal t
         t += 1
         for b, sc in enumerate(sc_list):
-            Q, K = ctxs[b].estimate_grad(th[b], sc.views, tg_list[b], sc.seed, t, sc.n_pairs, sc.eps)
+            Q, K = ctxs[b].estimate_grad(th[b], sc.views, tg_list[b], seed, t, sc.n_pairs, sc.eps)
             ctxs[b].step(th[b], m[b], v[b], t, Q, K, sc.eps, sc.n_pairs, kind=api.ADAM, averaging=api.AVG_COUNT,
                          lr=sc.lr)
 
@@ -292,7 +294,35 @@ def run_sequential_plain(sc_list, tg_list, steps, warmup, api, torch, dev, tile=
         one_step()
     stop.record()
     torch.cuda.synchronize()
-    return {"ms_per_step": start.elapsed_time(stop) / steps}
+    return {"ms_per_step": start.elapsed_time(stop) / steps, "ctxs": ctxs, "theta": th, "m": m, "v": v,
+            "steps_done": t}
+
+
+def batch_equality(g, p, sc_list, tg_list, seed, torch):
+    """Equal gradient accuracy of the two forms, checked on the runs just
+    timed: every scene's parameters and Adam moments after the same number
+    of steps from the same start, and then the Q and K of one more estimate
+    (the batch's against each scene's own context), compared bit for bit."""
+    bt = g["batch"]
+    torch.cuda.synchronize()
+    if bt.get_step() != p["steps_done"] + 1:
+        raise RuntimeError(f"step counters differ: batch at {bt.get_step()}, plain did {p['steps_done']}")
+    state_bad = [b for b in range(len(sc_list))
+                 if not (torch.equal(bt.theta[b], p["theta"][b]) and torch.equal(bt.m[b], p["m"][b])
+                         and torch.equal(bt.v[b], p["v"][b]))]
+    t = bt.get_step()
+    for b in range(len(sc_list)):
+        bt.Q[b].zero_()
+        bt.K[b].zero_()
+    bt.estimate()
+    est_bad = []
+    for b, sc in enumerate(sc_list):
+        Q, K = p["ctxs"][b].estimate_grad(bt.theta[b], sc.views, tg_list[b], seed, t, sc.n_pairs, sc.eps)
+        if not (torch.equal(Q, bt.Q[b]) and torch.equal(K, bt.K[b])):
+            est_bad.append(b)
+    torch.cuda.synchronize()
+    return {"scenes": len(sc_list), "steps_compared": p["steps_done"], "theta_m_v_equal": not state_bad,
+            "estimate_Q_K_equal": not est_bad, "differing_scenes": sorted(set(state_bad) | set(est_bad))}
 
 
 def main():
@@ -343,8 +373,10 @@ def main():
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     launches_per_step = tm["tile_launches"] / args.steps
     alg_bytes_launch = BYTES_PER_PIXEL_ESTIMATE * px_per_step / launches_per_step
-    # a one-scene batch runs the tile kernel with the scene in its arguments
-    kernel = f"k_tile<{tile},0,false>" if main_mode == "plain" else f"k_tile_b1<{tile}>"
+    # the graph-captured step is a one-scene batch, whose tile kernel takes the
+    # scene in its arguments; the host-driven modes (all items in one launch,
+    # or one launch per item) run the context's tile kernel
+    kernel = f"k_tile_b1<{tile}>" if main_mode == "graph" else f"k_tile<{tile},0,false>"
     traffic = measured_traffic(kernel) if args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
     out = {
@@ -399,7 +431,9 @@ def main():
 
 def main_batch64(args, torch, api, autotune, batch, scenes, dev):
     """64 independent scenes of uneven size: one graph-captured batched step
-    against 64 sequential plain steps (equal results, bit for bit)."""
+    against 64 sequential plain steps.  The two are then checked equal bit
+    for bit (parameters and moments after the timed steps, and one more
+    estimate's Q and K per scene); the run fails if any scene differs."""
     n = 64
     scs = [scenes.make_batch_scene(b) for b in range(n)]
     tgs = []
@@ -412,7 +446,12 @@ def main_batch64(args, torch, api, autotune, batch, scenes, dev):
     tile, caps, tune_report = autotune.tune_batch(scs, tgs, scs[0].n_pairs, dev, seed=scs[0].seed)
     progress(f"autotune: tile {tile}")
     g = run_graph_mode(scs, tgs, args.steps, args.warmup, api, batch, torch, dev, tile=tile, caps=caps)
-    p = run_sequential_plain(scs, tgs, args.steps, args.warmup, api, torch, dev, tile=tile, caps=caps)
+    progress(f"graph: {g['ms_per_step']:.3f} ms/step")
+    p = run_sequential_plain(scs, tgs, args.steps, args.warmup, api, torch, dev, tile=tile, caps=caps,
+                             seed=scs[0].seed)
+    progress(f"sequential plain: {p['ms_per_step']:.3f} ms/step")
+    eq = batch_equality(g, p, scs, tgs, scs[0].seed, torch)
+    progress(f"equality: {eq}")
     tm = g["timing"]
     tile_avg_ms = tm["tile_ms"] / max(tm["tile_launches"], 1)
     alg = BYTES_PER_PIXEL_ESTIMATE * px / (tm["tile_launches"] / args.steps)
@@ -435,8 +474,11 @@ def main_batch64(args, torch, api, autotune, batch, scenes, dev):
         "sequential_plain_steps_per_s": 1e3 / p["ms_per_step"],
         "speedup_vs_sequential_plain": p["ms_per_step"] / g["ms_per_step"],
         "pixel_estimates_per_s": px * 1e3 / g["ms_per_step"],
+        "equal_results": eq,
     }
     print(json.dumps(out), flush=True)
+    if eq["differing_scenes"]:
+        sys.exit(1)
 
 
 def main_soup(args, torch, api, scenes, dev):

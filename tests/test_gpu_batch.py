@@ -172,3 +172,54 @@ def test_batch_step_after_estimate_matches_plain(pairs):
         assert torch.equal(bt.theta[b], th[b]) and torch.equal(bt.m[b], m[b]) and torch.equal(bt.v[b], v[b])
         assert not bt.Q[b].any() and not bt.K[b].any()
     assert bt.get_step() == t + 1
+
+
+def test_sixteen_batch_config_scenes_match_plain_and_oracle():
+    """The batching configuration's own scenes (triangle counts log-uniform
+    in [1e3, 5e4], renders 128^2-1024^2, textures 128^2-1024^2, 4 pairs),
+    16 of them in one batch with the autotuned tile: one estimate equals each
+    scene's plain estimate (and, for two small scenes, the oracle's), and a
+    graph-captured step equals the plain steps, bit for bit."""
+    from paper_2404_09758_amd import autotune
+    scs = [S.make_batch_scene(b) for b in range(16)]
+    seed, t = scs[0].seed, 1
+    tgs = []
+    for sc in scs:
+        c = api.Context(sc, DEV)
+        tt = torch.tensor(sc.flat_params(True), device=DEV)
+        tgs.append(torch.cat([c.render(tt, v, ids=False, uv=False)[0].reshape(-1) for v in sc.views]))
+        del c
+    tile, caps, _ = autotune.tune_batch(scs, tgs, scs[0].n_pairs, DEV, seed=seed)
+    print(f"[batch16] tile {tile} caps {caps}", flush=True)
+    bt = batch.Batch(scs, scs[0].n_pairs, DEV, tile_px=tile, seed=seed, first_step=t, targets=tgs,
+                     bin_capacities=caps)
+    ctxs, th, m, v = [], [], [], []
+    for b, sc in enumerate(scs):
+        c = api.Context(sc, DEV, tuning=(tile, caps[b], 1))
+        c.set_scene_index(b)
+        ctxs.append(c)
+        th.append(bt.theta[b].clone())
+        m.append(bt.m[b].clone())
+        v.append(bt.v[b].clone())
+    bt.estimate()
+    for b, sc in enumerate(scs):
+        Q, K = ctxs[b].estimate_grad(th[b], sc.views, tgs[b], seed, t, sc.n_pairs, sc.eps)
+        assert torch.equal(Q, bt.Q[b]) and torch.equal(K, bt.K[b]), f"scene {b}"
+        if b in (8, 11):
+            o = oracle.Oracle(sc)
+            Qo, Ko, _, _ = o.estimate(sc.flat_params(), sc.views, [host(tgs[b]).reshape(-1)], seed, t,
+                                      sc.n_pairs, sc.eps, scene_index=b)
+            assert np.array_equal(host(bt.Q[b]), Qo) and np.array_equal(host(bt.K[b]).view(np.uint32), Ko)
+        bt.Q[b].zero_()
+        bt.K[b].zero_()
+    for step in (t, t + 1):
+        bt.step(use_graph=True)
+        for b, sc in enumerate(scs):
+            Q, K = ctxs[b].estimate_grad(th[b], sc.views, tgs[b], seed, step, sc.n_pairs, sc.eps)
+            ctxs[b].step(th[b], m[b], v[b], step, Q, K, sc.eps, sc.n_pairs, kind=api.ADAM,
+                         averaging=api.AVG_COUNT, lr=sc.lr)
+        torch.cuda.synchronize()
+        for b in range(len(scs)):
+            assert torch.equal(bt.theta[b], th[b]), f"step {step}, scene {b}"
+            assert torch.equal(bt.m[b], m[b]) and torch.equal(bt.v[b], v[b])
+    assert bt.stats()["tile_overflows"] == 0

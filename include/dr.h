@@ -249,6 +249,31 @@ dr_status dr_estimate_grad_image(dr_ctx* ctx, const float* theta, const dr_view*
                                  const float* grad_image, uint64_t seed, uint32_t step, int32_t n_pairs,
                                  const float* eps, int64_t* Q, uint32_t* K);
 
+/* dr_estimate_grad without any device allocation, for callers that cannot
+ * allocate: code being captured into a HIP graph, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, results (bit for bit)
+ * and errors as dr_estimate_grad, except that:
+ *  - all scratch (sign bits, triangle records, bins, per-pair group sums,
+ *    tessellated positions) comes from one static device array of
+ *    DR_NOALLOC_SCRATCH_BYTES, which every GPU the library is loaded on
+ *    holds until the process ends;
+ *  - a call whose scratch would exceed that size (after lowering the
+ *    items per raster launch as far as one) returns DR_E_INVALID and
+ *    launches nothing; dr_last_error states the bytes it needed;
+ *  - the bin capacity is the context's current one (no adaptive raise:
+ *    an overflowing bin is exact but slower), and no timing events are
+ *    recorded;
+ *  - every call on one GPU shares that GPU's array: calls that overlap on
+ *    one GPU (from several contexts or streams) race and give wrong
+ *    results.  Calls ordered on one stream are safe; each call clears the
+ *    part of the array that must start at zero.
+ * The array's device address is looked up by dr_create on the context's
+ * device; no call here allocates or frees memory. */
+#define DR_NOALLOC_SCRATCH_BYTES (128ull << 20)
+dr_status dr_estimate_grad_noalloc(dr_ctx* ctx, const float* theta, const dr_view* views, int32_t n_views,
+                                   const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                   const float* eps, int64_t* Q, uint32_t* K);
+
 /* Decode Q, K into float gradients: g_i = Q_i 2^-32 / (2 eps_i D_i) with
  * D_i = K of the parameter's group (DR_AVG_COUNT) or n_pairs (DR_AVG_PAIRS,
  * Eq. 9); 0 where eps_i = 0 or D_i = 0.  grad [d] float. */

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdr.so")
 MAX_TEX = 3
 MAX_VIEWS = 16
 BG_ID = 0xFFFFFFFF
+NOALLOC_SCRATCH_BYTES = 128 << 20      # DR_NOALLOC_SCRATCH_BYTES
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of device memory", -3: "HIP error", -4: "unsupported"}
 
@@ -87,6 +88,8 @@ SIGNATURES = {
                                         C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
     "dr_estimate_grad_image": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
                                          C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
+    "dr_estimate_grad_noalloc": (C.c_int, [_vp, _vp, C.POINTER(View), C.c_int32, _vp, C.c_uint64, C.c_uint32,
+                                           C.c_int32, C.POINTER(C.c_float), _vp, _vp]),
     "dr_subdivide_sizes": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "dr_subdivide": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),

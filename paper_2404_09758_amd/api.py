@@ -234,14 +234,18 @@ class Context:
         return Q, K
 
     def estimate_grad(self, theta, views: Sequence, targets, seed, step, n_pairs, eps, Q=None, K=None,
-                      full_image=False, image_grad=False):
+                      full_image=False, image_grad=False, noalloc=False):
         """Eq. 8 (per pixel) or, with full_image, Eq. 4, summed over pairs and
         views into Q, K.  targets: one float32 tensor holding the views'
         [H,W,3] images concatenated (or a list of them).  image_grad: targets
         hold dL/dI of a downstream loss instead, and each pixel scatters
-        <dL/dI, I+ - I-> (the image form; per pixel only)."""
+        <dL/dI, I+ - I-> (the image form; per pixel only).  noalloc: the
+        per-pixel loss form through dr_estimate_grad_noalloc, whose scratch
+        is the library's static device array (no device allocation)."""
         if full_image and image_grad:
             raise ValueError("the image form is a per-pixel estimator")
+        if noalloc and (full_image or image_grad):
+            raise ValueError("the allocation-free call is the per-pixel loss form")
         dp = _check_tensor(theta, torch.float32, self.device, self.d, "theta")
         if isinstance(targets, (list, tuple)):
             targets = torch.cat([t.reshape(-1) for t in targets])
@@ -253,6 +257,8 @@ class Context:
         dk = _check_tensor(K, torch.int32, self.device, self.G, "K")
         vws = (L.View * len(views))(*[make_view(v) for v in views])
         fn = "dr_estimate_grad_full" if full_image else ("dr_estimate_grad_image" if image_grad else "dr_estimate_grad")
+        if noalloc:
+            fn = "dr_estimate_grad_noalloc"
         self._call(fn, C.c_void_p(dp), vws, len(views),
                    C.c_void_p(dt), C.c_uint64(seed),
                    C.c_uint32(step), int(n_pairs), self._eps(eps), C.c_void_p(dq), C.c_void_p(dk))

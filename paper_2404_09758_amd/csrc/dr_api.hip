@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,8 @@ static dr_status fail(dr_ctx* c, dr_status s, const std::string& msg) {
     } while (0)
 
 static bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
+
+static hipError_t scratch_lookup(int dev, void** out);
 
 static dr_status device_guard(dr_ctx* c) {
     int cur = -1;
@@ -273,7 +276,21 @@ static dr_status setup_subdivision(dr_ctx* c, const dr_scene* s) {
 }
 
 // Subdivision surface: tessellate theta (perturbed as dp says) for
-// n_pairs x nsign (pair, sign) slots into c->fpos; *out = null otherwise.
+// n_pairs x nsign (pair, sign) slots into fpos (room for n_pairs * nsign *
+// n_verts * 3 floats); *out = null for a mesh whose vertices are the
+// parameters.
+static dr_status tessellate_into(dr_ctx* c, const float* theta, const DPert& dp, int n_pairs, int nsign,
+                                 float sgn0, float sgn1, float* fpos, bool timed, const float** out) {
+    *out = nullptr;
+    if (c->sc.n_ctrl == 0) return DR_OK;
+    auto go = [&] { return launch_subdiv(c->stream, c->sc, dp, theta, n_pairs, nsign, sgn0, sgn1, fpos); };
+    if (timed) HIPCHK(c, c->timer.run(c->stream, K_SETUP, go));
+    else HIPCHK(c, go());
+    *out = fpos;
+    return DR_OK;
+}
+
+// The same into the context's own buffer, grown as needed.
 static dr_status tessellate(dr_ctx* c, const float* theta, const DPert& dp, int n_pairs, int nsign, float sgn0,
                             float sgn1, const float** out) {
     *out = nullptr;
@@ -281,11 +298,7 @@ static dr_status tessellate(dr_ctx* c, const float* theta, const DPert& dp, int 
     dr_status s = grow(c, &c->fpos, &c->fpos_slots, (long long)n_pairs * nsign,
                        (size_t)c->sc.n_verts * 3 * sizeof(float), false);
     if (s) return s;
-    HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] {
-        return launch_subdiv(c->stream, c->sc, dp, theta, n_pairs, nsign, sgn0, sgn1, c->fpos);
-    }));
-    *out = c->fpos;
-    return DR_OK;
+    return tessellate_into(c, theta, dp, n_pairs, nsign, sgn0, sgn1, c->fpos, true, out);
 }
 
 extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning* tune, void* stream) {
@@ -413,6 +426,13 @@ extern "C" dr_status dr_create(dr_ctx** out, const dr_scene* s, const dr_tuning*
             delete c;
             return st;
         }
+    }
+    // the allocation-free estimate's scratch array on this device (its
+    // address is needed by dr_estimate_grad_noalloc only; a failed lookup
+    // is reported by that call)
+    {
+        void* p = nullptr;
+        (void)scratch_lookup(c->device, &p);
     }
     *out = c;
     return DR_OK;
@@ -597,37 +617,64 @@ static dr_status note_bins(dr_ctx* c) {
     return DR_OK;
 }
 
-static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
-                                 const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
-                                 const float* eps, int64_t* Q, uint32_t* K, bool full, bool image) {
+// Scratch of one estimate: where the sign bits, triangle records, bins,
+// per-pair group sums (or full-image totals) and tessellated positions go,
+// the bin capacity and the number of items per raster launch.
+struct EstScratch {
+    uint32_t* bits = nullptr;
+    TriR* recR = nullptr;
+    TriS* recS = nullptr;
+    unsigned* counts = nullptr;
+    unsigned* bins = nullptr;
+    long long* R = nullptr;
+    long long* qtot = nullptr;
+    float* fpos = nullptr;
+    int cap = 0;
+    long long per = 1;
+};
+
+// Validated arguments of an estimate.
+struct EstPlan {
+    DViews dv;
+    int max_tiles = 1;
+    long long items = 0;
+};
+
+static dr_status estimate_check(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                                const float* targets, int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K,
+                                EstPlan& pl) {
     if (!c) return DR_E_INVALID;
     if (!theta || !targets || !Q || !K || !views) return fail(c, DR_E_INVALID, "NULL array argument");
     if (n_views < 1 || n_views > DR_MAX_VIEWS) return fail(c, DR_E_INVALID, "n_views must be in [1, 16]");
     if (n_pairs < 1 || n_pairs > 65535) return fail(c, DR_E_INVALID, "n_pairs must be in [1, 65535]");
     dr_status s = check_eps(c, eps);
     if (s) return s;
-    s = device_guard(c);
-    if (s) return s;
-    s = adapt_capacity(c);
-    if (s) return s;
     int tile = c->tune.tile_px;
-    DViews dv;
-    std::memset(&dv, 0, sizeof(dv));
+    std::memset(&pl.dv, 0, sizeof(pl.dv));
     long long tgt_off = 0;
-    int max_tiles = 1;
+    pl.max_tiles = 1;
     for (int v = 0; v < n_views; ++v) {
         s = check_view(c, &views[v], tile);
         if (s) return s;
-        dv.v[v] = make_dview(views[v], tile, tgt_off);
+        pl.dv.v[v] = make_dview(views[v], tile, tgt_off);
         tgt_off += 3ll * views[v].width * views[v].height;
-        max_tiles = std::max(max_tiles, dv.v[v].tiles_x * dv.v[v].tiles_y);
+        pl.max_tiles = std::max(pl.max_tiles, pl.dv.v[v].tiles_x * pl.dv.v[v].tiles_y);
     }
-    s = device_guard(c);
-    if (s) return s;
-    long long items = (long long)n_pairs * n_views;
+    pl.items = (long long)n_pairs * n_views;
+    return DR_OK;
+}
+
+// Items per raster launch in the context's tuning (the grid y of the setup
+// launch is 2 * items <= 65535).
+static long long items_per_launch(const dr_ctx* c, long long items) {
     long long per = c->tune.items_per_launch == 0 ? items : std::min<long long>(items, c->tune.items_per_launch);
-    per = std::min<long long>(per, 32767);      // grid y of the setup launch is 2 * items <= 65535
-    s = ensure_raster(c, 2 * per, max_tiles);
+    return std::min<long long>(per, 32767);
+}
+
+// The context's own scratch, grown as needed.
+static dr_status estimate_scratch_ctx(dr_ctx* c, const EstPlan& pl, int32_t n_pairs, bool full, EstScratch& x) {
+    x.per = items_per_launch(c, pl.items);
+    dr_status s = ensure_raster(c, 2 * x.per, pl.max_tiles);
     if (s) return s;
     s = ensure_bits(c, n_pairs);
     if (s) return s;
@@ -638,18 +685,47 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
         s = grow(c, &c->R, &c->R_pairs, n_pairs, (size_t)c->sc.G * sizeof(long long), true);
         if (s) return s;
     }
+    if (c->sc.n_ctrl > 0) {
+        s = grow(c, &c->fpos, &c->fpos_slots, (long long)n_pairs * 2, (size_t)c->sc.n_verts * 3 * sizeof(float),
+                 false);
+        if (s) return s;
+    }
+    x.bits = c->bits;
+    x.recR = c->recR;
+    x.recS = c->recS;
+    x.counts = c->counts;
+    x.bins = c->bins;
+    x.R = c->R;
+    x.qtot = c->qtot;
+    x.fpos = c->fpos;
+    x.cap = c->tune.bin_capacity;
+    return DR_OK;
+}
 
+// Signs, (tessellation,) setup and tile launches, then the fold or the
+// full-image broadcast, on the scratch x.  timed: bracket the launches with
+// the context's timing events.
+static dr_status estimate_launch(dr_ctx* c, const EstPlan& pl, const float* theta, int32_t n_views,
+                                 const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                 const float* eps, int64_t* Q, uint32_t* K, bool full, bool image,
+                                 const EstScratch& x, bool timed) {
+    auto run = [&](int kind, auto launch) -> hipError_t {
+        return timed ? c->timer.run(c->stream, kind, launch) : launch();
+    };
+    int tile = c->tune.tile_px;
+    const int max_tiles = pl.max_tiles;
+    const long long items = pl.items, per = x.per;
     DPert dp;
-    dp.bits = c->bits;
+    dp.bits = x.bits;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) dp.eps[b] = (b < 1 + c->sc.n_tex) ? eps[b] : 0.0f;
-    HIPCHK(c, c->timer.run(c->stream, K_SIGNS, [&] {
-        return launch_signs(c->stream, seed, step, 0u, c->scene_index, c->sc.d, c->sc.words, n_pairs, c->bits);
+    HIPCHK(c, run(K_SIGNS, [&] {
+        return launch_signs(c->stream, seed, step, 0u, c->scene_index, c->sc.d, c->sc.words, n_pairs, x.bits);
     }));
 
     SetupArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.sc = c->sc;
-    sa.views = dv;
+    sa.views = pl.dv;
     sa.pert = dp;
     sa.theta = theta;
     sa.n_views = n_views;
@@ -657,33 +733,33 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
     sa.sgn[0] = 1.0f;
     sa.sgn[1] = -1.0f;
     sa.tile = tile;
-    sa.cap = c->tune.bin_capacity;
+    sa.cap = x.cap;
     sa.max_tiles = max_tiles;
-    sa.recR = c->recR;
-    sa.recS = c->recS;
-    sa.counts = c->counts;
-    sa.bins = c->bins;
+    sa.recR = x.recR;
+    sa.recS = x.recS;
+    sa.counts = x.counts;
+    sa.bins = x.bins;
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
     ta.sc = c->sc;
-    ta.views = dv;
+    ta.views = pl.dv;
     ta.pert = dp;
     ta.theta = theta;
     ta.n_views = n_views;
     ta.nsign = 2;
     ta.sgn[0] = 1.0f;
     ta.sgn[1] = -1.0f;
-    ta.cap = c->tune.bin_capacity;
+    ta.cap = x.cap;
     ta.max_tiles = max_tiles;
-    ta.recR = c->recR;
-    ta.recS = c->recS;
-    ta.counts = c->counts;
-    ta.bins = c->bins;
+    ta.recR = x.recR;
+    ta.recS = x.recS;
+    ta.counts = x.counts;
+    ta.bins = x.bins;
     ta.stats = c->stats;
     ta.targets = targets;
     ta.img_grad = image ? 1 : 0;
-    ta.R = c->R;
-    ta.qtot = c->qtot;
+    ta.R = x.R;
+    ta.qtot = x.qtot;
     ta.K = K;
     ta.act_pos = eps[0] != 0.0f;
     ta.any_act = ta.act_pos;
@@ -692,30 +768,47 @@ static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* v
             ta.act_cls[c->sc.tex_cls[t]] = 1;
             ta.any_act = 1;
         }
-    s = tessellate(c, theta, dp, n_pairs, 2, 1.0f, -1.0f, &sa.fpos);
+    dr_status s = tessellate_into(c, theta, dp, n_pairs, 2, 1.0f, -1.0f, x.fpos, timed, &sa.fpos);
     if (s) return s;
-    if (full) HIPCHK(c, launch_zero64(c->stream, c->qtot, n_pairs));
+    if (full) HIPCHK(c, launch_zero64(c->stream, x.qtot, n_pairs));
     for (long long i0 = 0; i0 < items; i0 += per) {
         int n = (int)std::min(per, items - i0);
         sa.item0 = (int)i0;
         ta.item0 = (int)i0;
-        HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
-        HIPCHK(c, c->timer.run(c->stream, K_TILE,
-                               [&] { return launch_tile(c->stream, ta, tile, full ? 3 : 0, n, max_tiles); }));
+        HIPCHK(c, run(K_SETUP, [&] { return launch_setup(c->stream, sa, n); }));
+        HIPCHK(c, run(K_TILE, [&] { return launch_tile(c->stream, ta, tile, full ? 3 : 0, n, max_tiles); }));
     }
     FoldArgs fa;
     std::memset(&fa, 0, sizeof(fa));
     fa.sc = c->sc;
-    fa.R = c->R;
-    fa.bits = c->bits;
+    fa.R = x.R;
+    fa.bits = x.bits;
     fa.n_pairs = n_pairs;
     for (int b = 0; b <= DRD_MAX_TEX; ++b) fa.eps[b] = dp.eps[b];
     fa.Q = (long long*)Q;
-    fa.qtot = c->qtot;
+    fa.qtot = x.qtot;
     fa.K = K;
     fa.n_views = n_views;
-    if (full) HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_broadcast(c->stream, fa); }));
-    else HIPCHK(c, c->timer.run(c->stream, K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    if (full) HIPCHK(c, run(K_FOLD, [&] { return launch_broadcast(c->stream, fa); }));
+    else HIPCHK(c, run(K_FOLD, [&] { return launch_fold(c->stream, fa); }));
+    return DR_OK;
+}
+
+static dr_status estimate_common(dr_ctx* c, const float* theta, const dr_view* views, int32_t n_views,
+                                 const float* targets, uint64_t seed, uint32_t step, int32_t n_pairs,
+                                 const float* eps, int64_t* Q, uint32_t* K, bool full, bool image) {
+    EstPlan pl;
+    dr_status s = estimate_check(c, theta, views, n_views, targets, n_pairs, eps, Q, K, pl);
+    if (s) return s;
+    s = device_guard(c);
+    if (s) return s;
+    s = adapt_capacity(c);
+    if (s) return s;
+    EstScratch x;
+    s = estimate_scratch_ctx(c, pl, n_pairs, full, x);
+    if (s) return s;
+    s = estimate_launch(c, pl, theta, n_views, targets, seed, step, n_pairs, eps, Q, K, full, image, x, true);
+    if (s) return s;
     return note_bins(c);
 }
 
@@ -736,6 +829,124 @@ extern "C" dr_status dr_estimate_grad_image(dr_ctx* c, const float* theta, const
                                             int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K) {
     return estimate_common(c, theta, views, n_views, grad_image, seed, step, n_pairs, eps, Q, K, false, true);
 }
+
+// ------------------------------------------------ allocation-free estimate --
+//
+// dr_estimate_grad_noalloc takes all of its scratch from one file-scope
+// device array instead of the context's buffers.  Every GPU the library is
+// loaded on holds its own copy of the array until the process ends.  In
+// host code the array's name stands for a host-side shadow, not for the
+// device memory, so it is never passed to a kernel or a copy: its device
+// address is looked up once per device (dr_create, with that device
+// current) and kept in scratch_dev[].
+
+static __device__ __align__(256) unsigned char scratch[DR_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex scratch_mu;
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static void* scratch_dev[SCRATCH_MAX_DEVICES];
+static hipError_t scratch_err[SCRATCH_MAX_DEVICES];
+static bool scratch_done[SCRATCH_MAX_DEVICES];
+
+// Device address of `scratch` on the current device `dev` (looked up on the
+// first call for that device).
+static hipError_t scratch_lookup(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_done[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        scratch_dev[dev] = p;
+        scratch_err[dev] = e;
+        scratch_done[dev] = true;
+    }
+    *out = scratch_dev[dev];
+    return scratch_err[dev];
+}
+
+static unsigned long long round256(unsigned long long b) { return (b + 255ull) & ~255ull; }
+
+// Layout of the estimate's scratch in the static array, items per launch
+// `per`: the bin counters and the per-pair group sums first (the part that
+// must start at zero), then the sign bits, the records, the bins and the
+// tessellated positions.  Returns the bytes needed; fills x when base is
+// given.
+static unsigned long long static_layout(const dr_ctx* c, const EstPlan& pl, int32_t n_pairs, long long per,
+                                        unsigned char* base, EstScratch* x, unsigned long long* zero_bytes) {
+    const DScene& sc = c->sc;
+    const unsigned long long slots = 2ull * (unsigned long long)per;
+    const unsigned long long cap = (unsigned long long)c->tune.bin_capacity;
+    unsigned long long off = 0;
+    auto take = [&](unsigned long long bytes) {
+        unsigned long long o = off;
+        off += round256(bytes);
+        return o;
+    };
+    const unsigned long long bin_slots = slots * (unsigned long long)pl.max_tiles;
+    unsigned long long o_counts = take(bin_slots * sizeof(unsigned));
+    unsigned long long o_R = take((unsigned long long)n_pairs * (unsigned long long)sc.G * sizeof(long long));
+    if (zero_bytes) *zero_bytes = off;
+    unsigned long long o_bits = take(((unsigned long long)n_pairs * (unsigned long long)sc.words + 1ull) * 4ull);
+    unsigned long long o_recR = take(slots * (unsigned long long)sc.n_tris * sizeof(TriR));
+    unsigned long long o_recS = take(slots * (unsigned long long)sc.n_tris * sizeof(TriS));
+    unsigned long long o_bins = take(bin_slots * cap * sizeof(unsigned));
+    unsigned long long o_fpos = 0;
+    if (sc.n_ctrl > 0) o_fpos = take((unsigned long long)n_pairs * 2ull * (unsigned long long)sc.n_verts * 12ull);
+    if (base && x) {
+        x->counts = (unsigned*)(base + o_counts);
+        x->R = (long long*)(base + o_R);
+        x->bits = (uint32_t*)(base + o_bits);
+        x->recR = (TriR*)(base + o_recR);
+        x->recS = (TriS*)(base + o_recS);
+        x->bins = (unsigned*)(base + o_bins);
+        x->fpos = sc.n_ctrl > 0 ? (float*)(base + o_fpos) : nullptr;
+        x->qtot = nullptr;
+        x->cap = (int)cap;
+        x->per = per;
+    }
+    return off;
+}
+
+extern "C" dr_status dr_estimate_grad_noalloc(dr_ctx* c, const float* theta, const dr_view* views,
+                                              int32_t n_views, const float* targets, uint64_t seed, uint32_t step,
+                                              int32_t n_pairs, const float* eps, int64_t* Q, uint32_t* K) {
+    EstPlan pl;
+    dr_status s = estimate_check(c, theta, views, n_views, targets, n_pairs, eps, Q, K, pl);
+    if (s) return s;
+    s = device_guard(c);
+    if (s) return s;
+    void* base = nullptr;
+    hipError_t e = scratch_lookup(c->device, &base);
+    if (e != hipSuccess || !base)
+        return fail(c, DR_E_HIP, std::string("device address of the static scratch array: ") + hipGetErrorString(e));
+    // as many items per raster launch as the tuning asks for and the array
+    // holds (the results do not depend on it); one at the least
+    long long per = items_per_launch(c, pl.items);
+    unsigned long long need = static_layout(c, pl, n_pairs, per, nullptr, nullptr, nullptr);
+    while (need > DR_NOALLOC_SCRATCH_BYTES && per > 1) {
+        per = (per + 1) / 2;
+        need = static_layout(c, pl, n_pairs, per, nullptr, nullptr, nullptr);
+    }
+    if (need > DR_NOALLOC_SCRATCH_BYTES)
+        return fail(c, DR_E_INVALID,
+                    "dr_estimate_grad_noalloc needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                        std::to_string((unsigned long long)DR_NOALLOC_SCRATCH_BYTES) +
+                        "-byte maximum (fewer pairs, fewer or smaller views, a smaller bin capacity, or "
+                        "dr_estimate_grad)");
+    EstScratch x;
+    unsigned long long zero_bytes = 0;
+    (void)static_layout(c, pl, n_pairs, per, (unsigned char*)base, &x, &zero_bytes);
+    // the array keeps the last call's contents: clear the bin counters and
+    // the group sums (a fill kernel, so the call can be captured in a graph)
+    HIPCHK(c, launch_zero64(c->stream, (long long*)base, (int)(zero_bytes / 8ull)));
+    return estimate_launch(c, pl, theta, n_views, targets, seed, step, n_pairs, eps, Q, K, false, false, x, false);
+}
+
 
 // --------------------------------------------------------------- loss --
 

@@ -536,8 +536,10 @@ def make_soup(n_tris: int, res: int = 512, seed: int = 7, pairs: int = 128) -> S
     """Triangle soup of the per-pixel vs full-image validation (Sec. 6.1):
     n_tris independent triangles, each with 12 parameters (its 3 vertices and
     one RGB colour), unlit, seen from the front.  The colour of triangle t is
-    texel t of a power-of-two colour map whose corner UVs all sit on that
-    texel's centre; nearest-texel mode credits only that texel.  The target
+    texel t of an h x w colour map with exactly n_tris texels (h the largest
+    divisor of n_tris not above its square root), whose corner UVs all sit
+    on that texel's centre; nearest-texel mode credits only that texel, so
+    d = 9 n_tris + 3 n_tris = 12 n_tris, the count of Sec. 6.1.  The target
     is a seeded value-noise image (the paper's target image is not
     available), so `target_pos`/`target_tex` are unused."""
     rng = np.random.default_rng(seed * 1000 + n_tris)
@@ -552,12 +554,8 @@ def make_soup(n_tris: int, res: int = 512, seed: int = 7, pairs: int = 128) -> S
     a, b, c = pos[tri[:, 0]], pos[tri[:, 1]], pos[tri[:, 2]]
     flip = np.cross(b - a, c - a)[:, 2] < 0                 # face the camera (+z)
     tri[flip] = tri[flip][:, [0, 2, 1]]
-    w = 1
-    while w * w < n_tris:
-        w *= 2
-    h = w
-    while (h // 2) * w >= n_tris:
-        h //= 2
+    h = max(k for k in range(1, math.isqrt(n_tris) + 1) if n_tris % k == 0)
+    w = n_tris // h
     tx, ty = np.arange(n_tris) % w, np.arange(n_tris) // w
     uv = np.stack([(tx + 0.5) / w, (ty + 0.5) / h], 1).astype(np.float32)
     corner_uv = np.repeat(uv[:, None, :], 3, axis=1)

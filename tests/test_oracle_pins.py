@@ -109,6 +109,18 @@ def test_param_count_matches_paper_table(oracle_lib):
         assert S.param_count(row["vertices"], [tuple(row["texture"])]) == row["d"]
 
 
+def test_soup_param_count_matches_sec_6_1():
+    """The triangle soups of the Sec. 6.1 validation have 12 parameters per
+    triangle (3 vertices and an RGB colour): d = 12 F for F = 1K, 10K, 100K,
+    the counts of Table 3's rows."""
+    g = json.load(open(os.path.join(GOLDEN, "param_counts.json")))
+    for row in g["triangle_soup"]:
+        sc = S.make_soup(row["triangles"], res=32)
+        assert sc.n_tris == row["triangles"]
+        assert sc.n_params == row["d"] == row["params_per_triangle"] * row["triangles"]
+        assert S.param_count(3 * sc.n_tris, [tuple(t.shape) for t in sc.tex]) == row["d"]
+
+
 # ---------------------------------------------------------------- raster ---
 
 def _single_tri_masks(sc, view):

@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="paper",
-                    choices=["paper", "mid", "tiny", "batch64", "soup", "layers", "subdiv"])
+                    choices=["paper", "mid", "tiny", "batch64", "soup", "layers", "subdiv", "atomics"])
     ap.add_argument("--soup-steps", type=int, default=100, help="Adam steps per run of the soup config")
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle: whole steps timed per core count")
     ap.add_argument("--no-cpu", action="store_true")
@@ -341,6 +341,8 @@ def main():
         return main_soup(args, torch, api, scenes, dev)
     if args.config == "layers":
         return main_layers(args, torch, api, autotune, scenes, dev)
+    if args.config == "atomics":
+        return main_atomics(args, torch, dev)
     sc = scenes.CONFIGS[args.config]()
     ctx = api.Context(sc, dev, tuning=(16, 256, 0))
     th0 = torch.tensor(sc.flat_params(), device=dev)
@@ -568,6 +570,53 @@ def main_layers(args, torch, api, autotune, scenes, dev):
            "steps": args.steps, "warmup": args.warmup,
            "config": {"workload": "layers: icosphere 20480 tris, 512^2 px, lambert, RGBA albedo 512^2, "
                                   "0 / 2 / 4 composited layers"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def main_atomics(args, torch, dev):
+    """The atomic ceiling of the scatter's flush: agent-scope 64- and 32-bit
+    atomic adds (no value returned) by address pattern -- adjacent lanes on
+    adjacent elements, one element per 128-byte line, hashed (as a flush of
+    hashed groups), and a wave's 64 lanes on one element -- into a 256 MiB
+    buffer, timed with HIP events on the launch stream (median of 5)."""
+    import statistics
+
+    from paper_2404_09758_amd import _lib as L
+    lib = L.load()
+    nbytes = 256 << 20
+    n_ops = 1 << 26
+    buf = torch.zeros(nbytes // 8, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    names = {L.PROBE_CONTIGUOUS: "contiguous", L.PROBE_LINES: "one_per_line", L.PROBE_SCATTERED: "scattered",
+             L.PROBE_CONFLICTING: "conflicting"}
+    rows = []
+    for width in (64, 32):
+        for pat, name in names.items():
+            def launch():
+                st = lib.dr_probe_atomics(buf.data_ptr(), nbytes, width, pat, n_ops, stream)
+                if st != 0:
+                    raise RuntimeError(f"dr_probe_atomics: {L.STATUS.get(st, st)}")
+            launch()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(5):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                launch()
+                b.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = statistics.median(times)
+            rows.append({"width_bits": width, "pattern": name, "ops": n_ops, "ms": ms,
+                         "atomics_per_s": n_ops / (ms * 1e-3),
+                         "operand_bytes_per_s": n_ops * width / 8 / (ms * 1e-3)})
+            progress(f"atomics {width}-bit {name}: {rows[-1]['atomics_per_s'] / 1e9:.1f} G/s")
+    out = {"metric": "agent-scope atomic adds per second by address pattern (256 MiB buffer)",
+           "unit": "atomics/s", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"atomics: {n_ops} no-return atomic adds per launch, 64- and 32-bit, "
+                                  "4 address patterns"},
            "rows": rows}
     print(json.dumps(out), flush=True)
 

@@ -351,6 +351,24 @@ dr_status dr_batch_timing_enable(dr_batch* b, int enable);
 dr_status dr_batch_timing_read(dr_batch* b, dr_timing_t* out, int reset);
 const char* dr_batch_last_error(const dr_batch* b);
 
+/* ---------------------------------------------------------- measurement
+ * Throughput probe of the device-scope atomic adds that the scatter's
+ * flush issues (Alg. 2 accumulates with AtomicAdd; here each tile adds its
+ * per-group sums with one 64-bit and one 32-bit agent-scope atomic per
+ * group).  Launches n_ops atomic adds of 1 (width_bits 32 or 64, no value
+ * returned) on the stream into the device buffer buf of `bytes` bytes
+ * (8-byte aligned, caller-owned; its contents are changed), operation i
+ * addressing element e(i) of the buffer, n = bytes / (width_bits / 8):
+ *   DR_PROBE_CONTIGUOUS   e = i mod n (adjacent lanes, adjacent elements)
+ *   DR_PROBE_LINES        e = (i * 128 / elem_bytes) mod n (one per 128 B line)
+ *   DR_PROBE_SCATTERED    e = hash(i) mod n (unrelated lines, as a flush of
+ *                         hashed groups)
+ *   DR_PROBE_CONFLICTING  e = (i / 64) mod n (a wave's 64 lanes on one element)
+ * Asynchronous; DR_E_INVALID for a bad argument (nothing launched). */
+enum { DR_PROBE_CONTIGUOUS = 0, DR_PROBE_LINES = 1, DR_PROBE_SCATTERED = 2, DR_PROBE_CONFLICTING = 3 };
+dr_status dr_probe_atomics(void* buf, int64_t bytes, int32_t width_bits, int32_t pattern, int64_t n_ops,
+                           void* stream);
+
 const char* dr_status_str(dr_status s);
 const char* dr_last_error(const dr_ctx* ctx);     /* "" when none; ctx may be NULL */
 

@@ -13,7 +13,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "dr_kernels.hip"), os.path.join(CSRC, "dr_api.hip"), os.path.join(CSRC, "dr_subdiv.cpp")]
+SOURCES = [os.path.join(CSRC, "dr_kernels.hip"), os.path.join(CSRC, "dr_api.hip"), os.path.join(CSRC, "dr_subdiv.cpp"),
+           os.path.join(CSRC, "dr_probe.hip")]
 OUT = os.path.join(HERE, "libdr.so")
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",

@@ -269,7 +269,11 @@ __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const 
     const bool pert = pb != nullptr && e != 0.0f;
     const DRD_GLOBAL uint32_t* pw = pb + (base >> 5);
     unsigned bb = (unsigned)(base & 31);
-    float es = (sgn > 0.0f) ? e : -e;
+    // s_i (sgn e) is e (>= 0) with its sign bit set to the sign bit s_i
+    // holds -- complemented for the minus render: the IEEE value of
+    // +-e exactly, so x + it is the same operation as pval's
+    const unsigned eb = __float_as_uint(e);
+    const unsigned flip = (sgn > 0.0f) ? 0u : 0xFFFFFFFFu;
     float wx[2] = {1.0f - f.fx, f.fx};
     float acc[C];
     // row by row (ya, then yb), two texels each: the weighted sum keeps its
@@ -281,8 +285,9 @@ __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const 
         // texel offsets within the texture: W, H <= 32768 and C <= 4 keep
         // them below 2^32
         unsigned o[2];
-        o[0] = ((unsigned)yy * (unsigned)W + (unsigned)f.xa) * C;
-        o[1] = ((unsigned)yy * (unsigned)W + (unsigned)f.xb) * C;
+        const unsigned ro = __umul24((unsigned)yy, (unsigned)W);      // W, H <= 32768: exact
+        o[0] = (ro + (unsigned)f.xa) * C;
+        o[1] = (ro + (unsigned)f.xb) * C;
         float x[2][C];
         if (C == 1 && f.xb == f.xa + 1) {
             // the row's two single-channel texels are adjacent: one 8 B read
@@ -315,9 +320,12 @@ __device__ __forceinline__ void sample_texels(const DRD_GLOBAL float* th, const 
                 win[1] = __builtin_amdgcn_alignbit((unsigned)(wb >> 32), (unsigned)wb, rb & 31u);
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 2; ++k) {
+                const unsigned wk = win[k] ^ flip;
 #pragma unroll
-                for (int c = 0; c < C; ++c) x[k][c] = x[k][c] + (((win[k] >> c) & 1u) ? -es : es);
+                for (int c = 0; c < C; ++c)
+                    x[k][c] = x[k][c] + __uint_as_float(((wk << (31 - c)) & 0x80000000u) | eb);
+            }
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {

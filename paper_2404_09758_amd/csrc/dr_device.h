@@ -68,26 +68,23 @@ struct DPert {
     float eps[1 + DRD_MAX_TEX];
 };
 
-// Raster half of a triangle record (64 B): snapped vertices in normalised
-// (positive-area) order, flags, the depth plane and the pixel bounding box.
-// The first 32 B hold all that the shading reads from it.
+// Raster half of a triangle record (48 B): snapped vertices in normalised
+// (positive-area) order, flags, 1 / area and the depth plane.  The first
+// 32 B hold all that the shading reads from it; the pixel box is recomputed
+// from the corners where it is needed (tri_box).
 struct __align__(16) TriR {
     int X[3], Y[3];
     unsigned flags;                      // bit0 valid, bit1+k top-left edge k, bit4 swapped
     float ia;                            // 1 / area2
     float z0, zx, zy;
-    short bx0, by0, bx1, by1;            // inclusive pixel bbox, clamped to the view
     int pad;
-    long long area2;
 };
 
-// Shading half (64 B): 1/w in normalised order, perturbed world positions
-// and vertex indices in the original corner order.
+// Shading half (48 B): 1/w in normalised order and the perturbed world
+// positions in the original corner order.
 struct __align__(16) TriS {
     float iw[3];
     float p[9];
-    int vid[3];
-    int pad;
 };
 
 // Per-face shading frame: the unit face normal and (GGX) the tangent frame
@@ -100,8 +97,8 @@ struct TriF {
     float B[3];
 };
 
-static_assert(sizeof(TriR) == 64, "TriR layout");
-static_assert(sizeof(TriS) == 64, "TriS layout");
+static_assert(sizeof(TriR) == 48, "TriR layout");
+static_assert(sizeof(TriS) == 48, "TriS layout");
 
 #define TRI_VALID 1u
 #define TRI_SWAPPED 16u
@@ -196,6 +193,19 @@ __device__ __forceinline__ bool inside_small(const TriR& r, int px, int py) {
     bool ok1 = (e1 > 0) || (e1 == 0 && (r.flags & 4u));
     bool ok2 = (e2 > 0) || (e2 == 0 && (r.flags & 8u));
     return ok0 && ok1 && ok2;
+}
+
+// Pixel box of a triangle clipped to [px0, cx1] x [py0, cy1] (px0, py0 >= 0):
+// the pixels whose centre 256 x + 128 lies within the snapped corners'
+// bounds.  Empty when x0 > x1 or y0 > y1.
+__device__ __forceinline__ void tri_box(const TriR& r, int px0, int py0, int cx1, int cy1, int& x0, int& x1,
+                                        int& y0, int& y1) {
+    int xmin = min(r.X[0], min(r.X[1], r.X[2])), xmax = max(r.X[0], max(r.X[1], r.X[2]));
+    int ymin = min(r.Y[0], min(r.Y[1], r.Y[2])), ymax = max(r.Y[0], max(r.Y[1], r.Y[2]));
+    x0 = max((xmin + 127) >> 8, px0);
+    x1 = min((xmax - 128) >> 8, cx1);
+    y0 = max((ymin + 127) >> 8, py0);
+    y1 = min((ymax - 128) >> 8, cy1);
 }
 
 __device__ __forceinline__ float depth_at(const TriR& r, int px, int py) {

@@ -102,7 +102,6 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) { r.X[k] = v[k].X; r.Y[k] = v[k].Y; sh.iw[k] = v[k].iw; }
-    r.area2 = area2;
     unsigned fl = TRI_VALID | (sw ? TRI_SWAPPED : 0u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -128,11 +127,8 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
     if (bx0 > bx1 || by0 > by1) {               // no pixel centre in the bbox
         bx0 = 1; bx1 = 0; by0 = 1; by1 = 0;
     }
-    r.bx0 = (short)bx0; r.bx1 = (short)bx1; r.by0 = (short)by0; r.by1 = (short)by1;
 #pragma unroll
     for (int k = 0; k < 9; ++k) sh.p[k] = p[k];
-    sh.vid[0] = vid[0]; sh.vid[1] = vid[1]; sh.vid[2] = vid[2];
-    sh.pad = 0;
     recR[t] = r;
     recS[t] = sh;
     if (bx0 > bx1) return;
@@ -271,11 +267,12 @@ __device__ __forceinline__ void raster_px(const TriR& r, unsigned t, int x, int 
     insert_key<DEEP>(key, (y - py0) * TILE + (x - px0), ((unsigned long long)__float_as_uint(z) << 32) | t, L);
 }
 
+// (cx1, cy1): the tile's last pixel inside the view.
 template <int TILE, bool DEEP>
-__device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, int py0, int lane,
-                                           unsigned long long* key, int L) {
-    int x0 = max((int)r.bx0, px0), x1 = min((int)r.bx1, px0 + TILE - 1);
-    int y0 = max((int)r.by0, py0), y1 = min((int)r.by1, py0 + TILE - 1);
+__device__ __forceinline__ void raster_tri(const TriR& r, unsigned t, int px0, int py0, int cx1, int cy1,
+                                           int lane, unsigned long long* key, int L) {
+    int x0, x1, y0, y1;
+    tri_box(r, px0, py0, cx1, cy1, x0, x1, y0, y1);
     if (x0 > x1 || y0 > y1) return;
     int bw = x1 - x0 + 1;
     int n = bw * (y1 - y0 + 1);
@@ -424,15 +421,14 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
 // 64-scene batch and the triangle soups).
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
-                                             int py0, int lane, unsigned long long* key, int L,
+                                             int py0, int cx1, int cy1, int lane, unsigned long long* key, int L,
                                              RasterStage* stage) {
     TriR r{};
     int x0 = 0, y0 = 0, bw = 1, c = 0;
     if ((unsigned)lane < n) {
         r = gload(&R[mine]);
         int x1, y1;
-        x0 = max((int)r.bx0, px0); x1 = min((int)r.bx1, px0 + TILE - 1);
-        y0 = max((int)r.by0, py0); y1 = min((int)r.by1, py0 + TILE - 1);
+        tri_box(r, px0, py0, cx1, cy1, x0, x1, y0, y1);
         if (x0 <= x1 && y0 <= y1) {
             bw = x1 - x0 + 1;
             c = bw * (y1 - y0 + 1);
@@ -457,8 +453,8 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
             TriR q;
             int* qw = reinterpret_cast<int*>(&q);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) qw[k] = __builtin_amdgcn_readlane(mw[k], j);
-            raster_tri<TILE, DEEP>(q, __builtin_amdgcn_readlane(mine, j), px0, py0, lane, key, L);
+            for (int k = 0; k < (int)(sizeof(TriR) / 4); ++k) qw[k] = __builtin_amdgcn_readlane(mw[k], j);
+            raster_tri<TILE, DEEP>(q, __builtin_amdgcn_readlane(mine, j), px0, py0, cx1, cy1, lane, key, L);
         }
         return;
     }
@@ -520,29 +516,30 @@ __device__ __forceinline__ void note_bin(unsigned long long* stats, unsigned c, 
 // One wave's batch of n <= 64 triangles, triangle `mine` held by lane < n.
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_group(const TriR* __restrict__ R, unsigned mine, unsigned n, int px0,
-                                             int py0, int lane, unsigned long long* key, int L,
+                                             int py0, int cx1, int cy1, int lane, unsigned long long* key, int L,
                                              RasterStage* stage) {
     if (n >= PACK_MIN_TRIS) {
-        raster_batch<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L, stage);
+        raster_batch<TILE, DEEP>(R, mine, n, px0, py0, cx1, cy1, lane, key, L, stage);
         return;
     }
     for (unsigned j = 0; j < n; ++j) {
         unsigned t = __builtin_amdgcn_readlane(mine, j);
         TriR r = gload(&R[t]);
-        raster_tri<TILE, DEEP>(r, t, px0, py0, lane, key, L);
+        raster_tri<TILE, DEEP>(r, t, px0, py0, cx1, cy1, lane, key, L);
     }
 }
 
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, unsigned cnt,
                                            const TriR* __restrict__ R, int wave, int nw, int lane, int px0,
-                                           int py0, unsigned long long* key, int L, RasterStage* stage) {
+                                           int py0, int cx1, int cy1, unsigned long long* key, int L,
+                                           RasterStage* stage) {
     for (unsigned base = (unsigned)wave; base < cnt; base += 64u * (unsigned)nw) {
         unsigned k = base + (unsigned)lane * (unsigned)nw;
         unsigned mine = k < cnt ? gload(&list[k]) : 0u;
         unsigned n = (cnt - base + (unsigned)nw - 1u) / (unsigned)nw;
         if (n > 64u) n = 64u;
-        raster_group<TILE, DEEP>(R, mine, n, px0, py0, lane, key, L, stage);
+        raster_group<TILE, DEEP>(R, mine, n, px0, py0, cx1, cy1, lane, key, L, stage);
     }
 }
 
@@ -553,20 +550,23 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
 // not one dependent record read per triangle.
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_scan(const TriR* __restrict__ R, int n_tris, int wave, int nw, int lane,
-                                            int px0, int py0, unsigned long long* key, int L,
+                                            int px0, int py0, int cx1, int cy1, unsigned long long* key, int L,
                                             RasterStage* stage) {
     for (int t0 = wave * 64; t0 < n_tris; t0 += 64 * nw) {
         int t = t0 + lane;
         bool hit = false;
         if (t < n_tris) {
             const TriR* q = &R[t];
+            TriR b;                                          // corners and flags (the first 28 B)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                b.X[k] = gload(&q->X[k]);
+                b.Y[k] = gload(&q->Y[k]);
+            }
             unsigned fl = gload(&q->flags);
-            unsigned b0 = gload(reinterpret_cast<const unsigned*>(&q->bx0));      // bx0 | by0 << 16
-            unsigned b1 = gload(reinterpret_cast<const unsigned*>(&q->bx1));      // bx1 | by1 << 16
-            int bx0 = (short)(b0 & 0xFFFFu), by0 = (short)(b0 >> 16);
-            int bx1 = (short)(b1 & 0xFFFFu), by1 = (short)(b1 >> 16);
-            hit = (fl & TRI_VALID) && bx0 <= bx1 && by0 <= by1 && bx0 <= px0 + TILE - 1 && bx1 >= px0 &&
-                  by0 <= py0 + TILE - 1 && by1 >= py0;
+            int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+            if (fl & TRI_VALID) tri_box(b, px0, py0, cx1, cy1, x0, x1, y0, y1);
+            hit = x0 <= x1 && y0 <= y1;
         }
         unsigned long long m = __ballot(hit);
         if (m == 0ull) continue;
@@ -575,7 +575,7 @@ __device__ __forceinline__ void raster_scan(const TriR* __restrict__ R, int n_tr
         // a permutation of the lanes: the hits to the front, in lane order
         int dst = hit ? below : n + (lane - below);
         unsigned mine = (unsigned)__builtin_amdgcn_ds_permute(dst * 4, t);
-        raster_group<TILE, DEEP>(R, mine, (unsigned)n, px0, py0, lane, key, L, stage);
+        raster_group<TILE, DEEP>(R, mine, (unsigned)n, px0, py0, cx1, cy1, lane, key, L, stage);
     }
 }
 
@@ -693,12 +693,9 @@ __device__ __forceinline__ void ctrl_union_add(GroupTable<LOG2T>& tb, long long*
 // their LDS anyway.
 #define TILE_MIN_WAVES 6
 
-// Group table slots: with a texel box (8- and 16-pixel tiles) the table
-// mostly holds vertex groups, so it is half the size it needs for texels.
 template <int TILE>
 struct TileCfg {
     static constexpr int LOG2T = TILE == 8 ? 9 : (TILE == 16 ? 10 : 11);
-    static constexpr int LOG2T_BOX = TILE == 8 ? 8 : 9;
 };
 
 
@@ -737,105 +734,22 @@ struct TileJob {
 // MODE: 0 estimate (both signs, scatter), 1 render (write rgb/id/uv),
 // 2 loss (per-tile sum of the per-pixel L2 error f_{w,h}), 3 full-image
 // estimate (both signs, per-tile sum of the fixed-point differences).
-// Texel box of a tile (estimate, one pixel per lane): the texel groups of
-// one texel class are summed in a direct-indexed LDS array over the
-// bounding box of the tile's footprint texels, row by row, instead of the
-// hashed table -- no hashing or probing per add, and the flush walks the
-// box in row order, so a wave's global atomics fall on runs of adjacent
-// groups.  The box's columns are the texel columns shifted by 0 or W / 2
-// (mod W), whichever gives the narrower box, so that a footprint across
-// the u seam stays compact.  A tile whose box would exceed BOX_CELLS uses
-// the table.
-template <int TILE>
-struct BoxCfg {
-    static constexpr int CELLS = TILE == 8 ? 256 : 1024;
-};
-
-template <int LOG2T, int CELLS>
-struct ScatterLDS {
-    GroupTable<LOG2T> table;
-    unsigned long long box[CELLS];          // packed sum and count, as the table
-};
-
 template <int TILE, int MODE>
 struct TileShared {
     static constexpr int NPIX = TILE * TILE;
     static constexpr int PPT = NPIX > 256 ? NPIX / 256 : 1;
     static constexpr int TB = NPIX / PPT;
-    static constexpr int NW = TB / 64;
     static constexpr int NS = (MODE == 0 || MODE == 3) ? 2 : 1;
-    static constexpr bool BOX = MODE == 0 && PPT == 1;
-    static constexpr int LOG2T = MODE == 0 ? (BOX ? TileCfg<TILE>::LOG2T_BOX : TileCfg<TILE>::LOG2T) : 1;
-    static constexpr int CELLS = BOX ? BoxCfg<TILE>::CELLS : 1;
+    static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
     unsigned long long key[NS][NPIX];
-    // the raster's per-wave stages, then (estimate) the group table and box
+    // the raster's per-wave stages, then (estimate) the group table
     union {
         RasterStage stage[TB / 64];
-        ScatterLDS<LOG2T, CELLS> sc;
+        GroupTable<LOG2T> table;
     } u;
     double red[MODE == 2 ? TB : 1];
     long long qred[MODE == 3 ? TB : 1];
-    int bred[BOX ? 6 : 1][NW];              // per-wave box bounds
-    unsigned nfl;                           // occupied table slots (flush)
-};
-
-// Minimum / maximum over the 64 lanes of a wave (DPP within rows of 16,
-// then row_bcast:15 and row_bcast:31), read from lane 63.  Every lane of
-// the wave must call them.
-__device__ __forceinline__ int wave_min(int v) {
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x111, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x112, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x114, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x118, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xa, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xc, 0xf, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x111, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x112, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x114, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x118, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x142, 0xa, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x143, 0xc, 0xf, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-// The footprint texels of one fragment in a class of width W: columns
-// xs[0..nx), rows ys[0..ny) (the bilinear 2 x 2, or the nearest texel).
-struct FootTexels {
-    int xs[2], ys[2];
-    int nx, ny;
-};
-
-__device__ __forceinline__ FootTexels foot_texels(float u, float v, int W, int H, int nearest) {
-    Foot f = footprint(u, v, W, H);
-    FootTexels t;
-    if (nearest) {
-        t.xs[0] = (f.fx >= 0.5f) ? f.xb : f.xa;
-        t.ys[0] = (f.fy >= 0.5f) ? f.yb : f.ya;
-        t.xs[1] = t.xs[0];
-        t.ys[1] = t.ys[0];
-        t.nx = 1;
-        t.ny = 1;
-    } else {
-        t.xs[0] = f.xa;
-        t.xs[1] = f.xb;
-        t.ys[0] = f.ya;
-        t.ys[1] = f.yb;
-        t.nx = 2;
-        t.ny = 2;
-    }
-    return t;
-}
-
-// The tile's texel box of one class.
-struct TexBox {
-    int use;                 // the box is in use (else the table takes the class)
-    int ylo, ulo, bw, bh;    // first row, first shifted column, width, height
-    int shift;               // column shift: 0 or W / 2
-    unsigned m;              // ceil(2^32 / bw): cell / bw as a multiply-high
+    unsigned nfl;                        // occupied table slots (flush)
 };
 
 template <int TILE, int MODE>
@@ -849,6 +763,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     const DView& vw = *J.vw;
     int tx = J.tile % vw.tiles_x, ty = J.tile / vw.tiles_x;
     int px0 = tx * TILE, py0 = ty * TILE;
+    const int cx1 = min(px0 + TILE - 1, vw.W - 1), cy1 = min(py0 + TILE - 1, vw.H - 1);   // last pixel in view
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int j = tid; j < NS * NPIX; j += TB) (&S.key[0][0])[j] = ~0ull;
@@ -874,10 +789,10 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             unsigned cnt = counts[J.tile];
             if (wv == 0 && lane == 0) note_bin(J.stats, cnt, (unsigned)J.cap);
             if (cnt <= (unsigned)J.cap)
-                raster_bin<TILE, false>(bins + (long long)J.tile * J.cap, cnt, R, wv, NWS, lane, px0, py0, key, 1,
-                                        &S.u.stage[wave]);
+                raster_bin<TILE, false>(bins + (long long)J.tile * J.cap, cnt, R, wv, NWS, lane, px0, py0, cx1, cy1,
+                                        key, 1, &S.u.stage[wave]);
             else
-                raster_scan<TILE, false>(R, sc.n_tris, wv, NWS, lane, px0, py0, key, 1, &S.u.stage[wave]);
+                raster_scan<TILE, false>(R, sc.n_tris, wv, NWS, lane, px0, py0, cx1, cy1, key, 1, &S.u.stage[wave]);
         }
     }
     __syncthreads();
@@ -886,27 +801,12 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
         counts[J.tile] = 0u;
     }
     if constexpr (MODE == 0) {
-        // the stages are done with: the group table and box take their place
+        // the stages are done with: the group table takes their place
         if (tid == 0) S.nfl = 0u;
         for (int j = tid; j < TSIZE; j += TB) {
-            S.u.sc.table.key[j] = HASH_EMPTY;
-            S.u.sc.table.sum[j] = 0ull;
+            S.u.table.key[j] = HASH_EMPTY;
+            S.u.table.sum[j] = 0ull;
         }
-        if constexpr (SH::BOX)
-            for (int j = tid; j < SH::CELLS; j += TB) S.u.sc.box[j] = 0ull;
-    }
-    // texel box (estimate, one pixel per lane): its class is the first
-    // scattered texel class
-    TexBox bx;
-    bx.use = 0; bx.ylo = 0; bx.ulo = 0; bx.bw = 1; bx.bh = 1; bx.shift = 0; bx.m = 0u;
-    int bc = -1;
-    if constexpr (SH::BOX) {
-        if (J.any_act)
-            for (int c = 0; c < sc.n_cls; ++c)
-                if (J.act_cls[c]) {
-                    bc = c;
-                    break;
-                }
     }
 
     double loss_acc = 0.0;
@@ -970,77 +870,11 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 q = quantize(pixel_delta(rgb[0], rgb[1], J.targets + 3 * pix, J.img), flag);
                 if (flag) atomicAdd(&J.stats[flag == 1 ? ST_SATURATIONS : ST_NONFINITE], 1ull);
             }
-            if constexpr (SH::BOX) {
-                // the box of class bc: bounds of the footprint texels of the
-                // tile's active pixels in both renders (rows; columns as
-                // they are and shifted by W / 2), over the block
-                int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
-                int W = 1, H = 1, hw = 0;
-                if (bc >= 0) {
-                    W = sc.cls_w[bc];
-                    H = sc.cls_h[bc];
-                    hw = W >> 1;
-                }
-                if (bc >= 0 && act) {
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) {
-                        if (id[s] == DRD_BG) continue;
-                        FootTexels t = foot_texels(uv[s][0], uv[s][1], W, H, sc.tex_mode == 1);
-                        lo[0] = min(lo[0], t.ys[0]);
-                        hi[0] = max(hi[0], t.ys[1]);     // ys[1] >= ys[0] (equal when nearest)
-#pragma unroll
-                        for (int k = 0; k < 2; ++k) {
-                            if (k >= t.nx) continue;
-                            int a = t.xs[k], b = (a + hw >= W) ? a + hw - W : a + hw;
-                            lo[1] = min(lo[1], a);
-                            hi[1] = max(hi[1], a);
-                            lo[2] = min(lo[2], b);
-                            hi[2] = max(hi[2], b);
-                        }
-                    }
-                }
-                if (bc >= 0) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        int mn = wave_min(lo[k]), mx = wave_max(hi[k]);
-                        if (lane == 0) {
-                            S.bred[k][wave] = mn;
-                            S.bred[3 + k][wave] = mx;
-                        }
-                    }
-                }
-                __syncthreads();                 // the table and box are cleared; the bounds are in
-                if (bc >= 0) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        int mn = S.bred[k][0], mx = S.bred[3 + k][0];
-#pragma unroll
-                        for (int w = 1; w < SH::NW; ++w) {
-                            mn = min(mn, S.bred[k][w]);
-                            mx = max(mx, S.bred[3 + k][w]);
-                        }
-                        lo[k] = __builtin_amdgcn_readfirstlane(mn);
-                        hi[k] = __builtin_amdgcn_readfirstlane(mx);
-                    }
-                    if (hi[0] >= 0) {
-                        int spa = hi[1] - lo[1], spb = hi[2] - lo[2];
-                        bool sh = spb < spa;
-                        bx.shift = sh ? hw : 0;
-                        bx.ulo = sh ? lo[2] : lo[1];
-                        bx.bw = (sh ? spb : spa) + 1;
-                        bx.bh = hi[0] - lo[0] + 1;
-                        bx.ylo = lo[0];
-                        bx.use = bx.bw * bx.bh <= SH::CELLS;
-                        bx.m = (unsigned)((0xFFFFFFFFull + (unsigned long long)bx.bw) / (unsigned long long)bx.bw);
-                    }
-                }
-            } else {
-                if (j == 0) __syncthreads();     // the group table is cleared
-            }
+            if (j == 0) __syncthreads();         // the group table is cleared
             if (J.act_pos && sc.n_ctrl > 0) {
                 bool same = act && id[0] == id[1];
-                wave_ctrl<LOG2T>(S.u.sc.table, J.Rp, J.K, sc, same, id[0], q);
-                if (act && !same) ctrl_union_add<LOG2T>(S.u.sc.table, J.Rp, J.K, sc, id[0], id[1], q);
+                wave_ctrl<LOG2T>(S.u.table, J.Rp, J.K, sc, same, id[0], q);
+                if (act && !same) ctrl_union_add<LOG2T>(S.u.table, J.Rp, J.K, sc, id[0], id[1], q);
             } else if (J.act_pos && act) {
                 // the union of the two renders' triangles' vertices, each once
                 int v0[3] = {-1, -1, -1};
@@ -1048,7 +882,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         v0[k] = gload(&sc.tri[3 * (long long)id[0] + k]);
-                        table_add<LOG2T>(S.u.sc.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
+                        table_add<LOG2T>(S.u.table, J.Rp, J.K, (unsigned)v0[k], q, 1u);
                     }
                 }
                 if (id[1] != DRD_BG && id[1] != id[0]) {
@@ -1056,49 +890,13 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                     for (int k = 0; k < 3; ++k) {
                         int g = gload(&sc.tri[3 * (long long)id[1] + k]);
                         bool dup = (g == v0[0]) || (g == v0[1]) || (g == v0[2]);
-                        if (!dup) table_add<LOG2T>(S.u.sc.table, J.Rp, J.K, (unsigned)g, q, 1u);
+                        if (!dup) table_add<LOG2T>(S.u.table, J.Rp, J.K, (unsigned)g, q, 1u);
                     }
                 }
             }
             if (act) {
                 for (int c = 0; c < sc.n_cls; ++c) {
                     if (!J.act_cls[c]) continue;
-                    if (SH::BOX && bx.use && c == bc) {
-                        // box cells of both renders' footprint texels, each once
-                        int W = sc.cls_w[c], H = sc.cls_h[c], hw = W >> 1;
-                        int cell[NS][4];
-#pragma unroll
-                        for (int s = 0; s < NS; ++s) {
-                            cell[s][0] = cell[s][1] = cell[s][2] = cell[s][3] = -1;
-                            if (id[s] == DRD_BG) continue;
-                            FootTexels t = foot_texels(uv[s][0], uv[s][1], W, H, sc.tex_mode == 1);
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                int kx = k & 1, ky = k >> 1;
-                                if (kx >= t.nx || ky >= t.ny) continue;
-                                int x = t.xs[kx], u = (x + bx.shift >= W) ? x + bx.shift - W : x + bx.shift;
-                                cell[s][k] = (t.ys[ky] - bx.ylo) * bx.bw + (u - bx.ulo);
-                            }
-                        }
-#pragma unroll
-                        for (int s = 0; s < NS; ++s)
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                int e = cell[s][k];
-                                if (e < 0) continue;
-                                bool dup = false;
-#pragma unroll
-                                for (int k2 = 0; k2 < 4; ++k2)
-                                    if (k2 < k && cell[s][k2] == e) dup = true;
-                                if (s == 1) {
-#pragma unroll
-                                    for (int k2 = 0; k2 < 4; ++k2)
-                                        if (cell[0][k2] == e) dup = true;
-                                }
-                                if (!dup) atomicAdd(&S.u.sc.box[e], pack_sc(q, 1u));
-                            }
-                        continue;
-                    }
                     int W = sc.cls_w[c], H = sc.cls_h[c];
                     unsigned base = (unsigned)sc.cls_goff[c];
                     unsigned gs[NS][4];
@@ -1133,7 +931,7 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                                 for (int j2 = 0; j2 < 4; ++j2)
                                     if (gs[0][j2] == g) dup = true;
                             }
-                            if (!dup) table_add<LOG2T>(S.u.sc.table, J.Rp, J.K, g, q, 1u);
+                            if (!dup) table_add<LOG2T>(S.u.table, J.Rp, J.K, g, q, 1u);
                         }
                 }
             }
@@ -1161,36 +959,13 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     }
     if constexpr (MODE == 0) {
         __syncthreads();
-        if constexpr (SH::BOX) {
-            // the box in row order: a wave's atomics go to runs of adjacent
-            // groups of a texel row
-            if (bx.use) {
-                const int n = bx.bw * bx.bh;
-                const int W = sc.cls_w[bc];
-                const long long goff = sc.cls_goff[bc];
-                const unsigned long long m = bx.m;
-                for (int e = tid; e < n; e += TB) {
-                    unsigned long long w = S.u.sc.box[e];
-                    if (w == 0ull) continue;
-                    long long q;
-                    unsigned c;
-                    unpack_sc(w, q, c);
-                    int row = (int)(((unsigned long long)(unsigned)e * m) >> 32);
-                    int col = e - row * bx.bw;
-                    int x = bx.ulo + col - bx.shift;
-                    if (x < 0) x += W;
-                    global_add(J.Rp, J.K, goff + (long long)(__umul24((unsigned)(bx.ylo + row), (unsigned)W) + (unsigned)x),
-                               q, c);
-                }
-            }
-        }
         if constexpr (TILE >= 16) {
             // occupied slots first gathered into a dense list (in the key
             // buffers, free by now and large enough from 16-pixel tiles
             // on), so the global atomics go out in full waves
             unsigned* list = reinterpret_cast<unsigned*>(&S.key[0][0]);
             for (int j = tid; j < TSIZE; j += TB) {
-                bool occ = S.u.sc.table.key[j] != HASH_EMPTY;
+                bool occ = S.u.table.key[j] != HASH_EMPTY;
                 unsigned long long m = __ballot(occ);
                 unsigned base = 0;
                 if (lane == 0 && m) base = atomicAdd(&S.nfl, (unsigned)__popcll(m));
@@ -1203,16 +978,16 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
                 unsigned j = list[i];
                 long long q;
                 unsigned c;
-                unpack_sc(S.u.sc.table.sum[j], q, c);
-                global_add(J.Rp, J.K, (long long)S.u.sc.table.key[j], q, c);
+                unpack_sc(S.u.table.sum[j], q, c);
+                global_add(J.Rp, J.K, (long long)S.u.table.key[j], q, c);
             }
         } else {
             for (int j = tid; j < TSIZE; j += TB) {
-                unsigned g = S.u.sc.table.key[j];
+                unsigned g = S.u.table.key[j];
                 if (g != HASH_EMPTY) {
                     long long q;
                     unsigned c;
-                    unpack_sc(S.u.sc.table.sum[j], q, c);
+                    unpack_sc(S.u.table.sum[j], q, c);
                     global_add(J.Rp, J.K, (long long)g, q, c);
                 }
             }
@@ -1277,6 +1052,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
     const int L = sc.layers;
     int tx = J.tile % vw.tiles_x, ty = J.tile / vw.tiles_x;
     int px0 = tx * TILE, py0 = ty * TILE;
+    const int cx1 = min(px0 + TILE - 1, vw.W - 1), cy1 = min(py0 + TILE - 1, vw.H - 1);   // last pixel in view
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int j = tid; j < NS * NPIX * LM; j += TB) (&S.key[0][0])[j] = ~0ull;
@@ -1294,10 +1070,10 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         if (tid == 0) note_bin(J.stats, cnt, (unsigned)J.cap);
         const TriR* __restrict__ R = J.recR[s];
         if (cnt <= (unsigned)J.cap)
-            raster_bin<TILE, true>(J.bins[s] + (long long)J.tile * J.cap, cnt, R, wave, NW, lane, px0, py0,
+            raster_bin<TILE, true>(J.bins[s] + (long long)J.tile * J.cap, cnt, R, wave, NW, lane, px0, py0, cx1, cy1,
                                    S.key[s], L, nullptr);
         else
-            raster_scan<TILE, true>(R, sc.n_tris, wave, NW, lane, px0, py0, S.key[s], L, nullptr);
+            raster_scan<TILE, true>(R, sc.n_tris, wave, NW, lane, px0, py0, cx1, cy1, S.key[s], L, nullptr);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1409,20 +1185,22 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                 if (k1 == ~0ull) continue;
                 unsigned id1 = (unsigned)(k1 & 0xFFFFFFFFull);
                 if (J.act_pos) {
-                    TriS sh1 = (s1 ? J.recS[1] : J.recS[0])[id1];
+                    int v1[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) v1[k] = gload(&sc.tri[3 * (long long)id1 + k]);
                     bool dup[3] = {false, false, false};
                     for (int e2 = 0; e2 < e; ++e2) {
                         unsigned long long k2 = (&S.key[0][0])[((e2 / L) * NPIX + local) * LM + e2 % L];
                         if (k2 == ~0ull) continue;
-                        TriS sh2 = (e2 >= L ? J.recS[1] : J.recS[0])[(unsigned)(k2 & 0xFFFFFFFFull)];
+                        const int* t2 = sc.tri + 3 * (long long)(unsigned)(k2 & 0xFFFFFFFFull);
+                        int v2[3] = {gload(&t2[0]), gload(&t2[1]), gload(&t2[2])};
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
-                            dup[k] = dup[k] || sh1.vid[k] == sh2.vid[0] || sh1.vid[k] == sh2.vid[1] ||
-                                     sh1.vid[k] == sh2.vid[2];
+                            dup[k] = dup[k] || v1[k] == v2[0] || v1[k] == v2[1] || v1[k] == v2[2];
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)sh1.vid[k], q, 1u);
+                        if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)v1[k], q, 1u);
                 }
                 if (J.any_act && sc.n_cls > 0) {
                     Attr a1 = frag_attr(sc, (s1 ? J.recR[1] : J.recR[0])[id1], (s1 ? J.recS[1] : J.recS[0])[id1],

@@ -341,7 +341,10 @@ dr_status dr_batch_destroy(dr_batch* b);
 dr_status dr_batch_estimate(dr_batch* b);
 /* One optimisation step of every scene (estimate, then descent), after
  * which the step counter advances.  use_graph != 0 captures the step as a
- * HIP graph on first use and replays it afterwards. */
+ * HIP graph on first use and replays it afterwards.  The step adds to its
+ * estimate whatever Q holds when Q may be non-zero -- on the first step,
+ * and after dr_batch_estimate (such a step runs without the graph) -- and
+ * leaves Q zero; Q must not be written between steps otherwise. */
 dr_status dr_batch_step(dr_batch* b, int use_graph);
 dr_status dr_batch_set_step(dr_batch* b, uint32_t step);      /* synchronous; step >= 1 */
 dr_status dr_batch_get_step(dr_batch* b, uint32_t* step);     /* synchronous */
@@ -368,6 +371,17 @@ const char* dr_batch_last_error(const dr_batch* b);
 enum { DR_PROBE_CONTIGUOUS = 0, DR_PROBE_LINES = 1, DR_PROBE_SCATTERED = 2, DR_PROBE_CONFLICTING = 3 };
 dr_status dr_probe_atomics(void* buf, int64_t bytes, int32_t width_bits, int32_t pattern, int64_t n_ops,
                            void* stream);
+
+/* Self-check of the shading's short correctly rounded sequences: for every
+ * float whose bit pattern lies in [lo, hi] (lo <= hi), the library's fast
+ * square root (op DR_PROBE_SQRT, valid for [2^-96, 2^126]) or reciprocal
+ * (DR_PROBE_RCP, valid for magnitudes in [2^-125, 2^125]) against the
+ * compiler's correctly rounded sqrtf or 1.0f / x.  Adds the number of
+ * operands where they differ to *bad and lowers *first to the least such
+ * bit pattern (device pointers; the caller sets them to 0 and 0xFFFFFFFF).
+ * Asynchronous on the stream. */
+enum { DR_PROBE_SQRT = 0, DR_PROBE_RCP = 1 };
+dr_status dr_probe_math(int32_t op, uint32_t lo, uint32_t hi, uint64_t* bad, uint32_t* first, void* stream);
 
 const char* dr_status_str(dr_status s);
 const char* dr_last_error(const dr_ctx* ctx);     /* "" when none; ctx may be NULL */

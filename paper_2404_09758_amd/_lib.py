@@ -16,6 +16,7 @@ BG_ID = 0xFFFFFFFF
 NOALLOC_SCRATCH_BYTES = 128 << 20      # DR_NOALLOC_SCRATCH_BYTES
 
 PROBE_CONTIGUOUS, PROBE_LINES, PROBE_SCATTERED, PROBE_CONFLICTING = 0, 1, 2, 3
+PROBE_SQRT, PROBE_RCP = 0, 1
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of device memory", -3: "HIP error", -4: "unsupported"}
 
@@ -116,6 +117,7 @@ SIGNATURES = {
     "dr_batch_timing_read": (C.c_int, [_vp, C.POINTER(Timing), C.c_int]),
     "dr_batch_last_error": (C.c_char_p, [_vp]),
     "dr_probe_atomics": (C.c_int, [_vp, C.c_int64, C.c_int32, C.c_int32, C.c_int64, _vp]),
+    "dr_probe_math": (C.c_int, [C.c_int32, C.c_uint32, C.c_uint32, _vp, _vp, _vp]),
     "dr_status_str": (C.c_char_p, [C.c_int]),
     "dr_last_error": (C.c_char_p, [_vp]),
 }

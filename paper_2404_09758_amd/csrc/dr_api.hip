@@ -1180,6 +1180,7 @@ struct dr_batch {
     std::vector<void*> allocs;
     unsigned long long* stats = nullptr;
     Timer timer;                       // direct launches only (not graph replays)
+    bool q_dirty = true;               // Q may hold sums (set at creation and by dr_batch_estimate)
 };
 
 static dr_status bfail(dr_batch* b, dr_status s, const std::string& msg) {
@@ -1461,6 +1462,7 @@ extern "C" dr_status dr_batch_estimate(dr_batch* b) {
     dr_status s = batch_device(b);
     if (s) return s;
     BHIPCHK(b, batch_enqueue(b, b->stream, false, true));
+    b->q_dirty = true;                   // Q now holds the estimate
     return DR_OK;
 }
 
@@ -1468,11 +1470,17 @@ extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
     if (!b) return DR_E_INVALID;
     dr_status s = batch_device(b);
     if (s) return s;
-    if (!use_graph) {
+    // A step reads Q only while it may hold sums (at creation, or after
+    // dr_batch_estimate); a step leaves it zero.  The graph is captured
+    // reading no Q, so a step with Q possibly non-zero runs directly.
+    if (!use_graph || b->q_dirty) {
+        b->args.q_zero = b->q_dirty ? 0 : 1;
         BHIPCHK(b, batch_enqueue(b, b->stream, true, true));
+        b->q_dirty = false;
         return DR_OK;
     }
     if (!b->exec) {
+        b->args.q_zero = 1;
         // capture on a stream of our own (the caller's may be the null
         // stream, which cannot be captured); order it after the caller's
         // stream with events on every replay

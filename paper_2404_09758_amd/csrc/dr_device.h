@@ -363,10 +363,54 @@ __device__ __forceinline__ void sample_tex(const DScene& sc, const float* __rest
     else sample_texels<2>(gth, gpb, base, W, e, sgn, f, out);
 }
 
+// Correctly rounded square root and reciprocal for operands in a normal
+// range, in fewer instructions than the general sequences.
+// sqrt_rn: for x in [2^-96, 2^126] the hardware square root (within 1 ulp)
+// corrected by the residuals of its two neighbours -- the correction the
+// compiler's sqrtf applies, without its scaling of tiny inputs and its
+// handling of 0, inf and NaN.  rcp_rn: for |y| in [2^-125, 2^125] the
+// hardware reciprocal refined by one Newton step with fused multiply-adds.
+// Both are checked against sqrtf and 1.0f / y for every operand of those
+// ranges (dr_probe_math); operands outside them take sqrtf and division.
+#define DRD_SQRT_LO 0x0F800000u        // 2^-96
+#define DRD_SQRT_HI 0x7E800000u        // 2^126
+#define DRD_RCP_LO 0x01000000u         // 2^-125
+#define DRD_RCP_HI 0x7E000000u         // 2^125
+
+__device__ __forceinline__ float sqrt_rn_fast(float x) {
+    float s = __builtin_amdgcn_sqrtf(x);
+    float sm = __uint_as_float(__float_as_uint(s) - 1u), sp = __uint_as_float(__float_as_uint(s) + 1u);
+    float rm = __builtin_fmaf(-sm, s, x), rp = __builtin_fmaf(-sp, s, x);
+    s = (rm <= 0.0f) ? sm : s;
+    return (rp > 0.0f) ? sp : s;
+}
+
+__device__ __forceinline__ float rcp_rn_fast(float y) {
+    float r = __builtin_amdgcn_rcpf(y);
+    float e = __builtin_fmaf(-y, r, 1.0f);
+    return __builtin_fmaf(e, r, r);
+}
+
+__device__ __forceinline__ bool sqrt_fast_ok(float x) {
+    unsigned b = __float_as_uint(x);
+    return b >= DRD_SQRT_LO && b <= DRD_SQRT_HI;            // positive, in range
+}
+
+__device__ __forceinline__ bool rcp_fast_ok(float y) {
+    unsigned b = __float_as_uint(y) & 0x7FFFFFFFu;
+    return b >= DRD_RCP_LO && b <= DRD_RCP_HI;
+}
+
+// sqrtf(x), correctly rounded
+__device__ __forceinline__ float sqrt_rn(float x) { return sqrt_fast_ok(x) ? sqrt_rn_fast(x) : sqrtf(x); }
+
+// 1.0f / y, correctly rounded
+__device__ __forceinline__ float rcp_rn(float y) { return rcp_fast_ok(y) ? rcp_rn_fast(y) : 1.0f / y; }
+
 __device__ __forceinline__ void nrm3(float* x) {
     float l2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
     if (l2 > 0.0f) {
-        float inv = 1.0f / sqrtf(l2);
+        float inv = rcp_rn(sqrt_rn(l2));                     // 1 / sqrt(l2), each correctly rounded
         x[0] = x[0] * inv; x[1] = x[1] * inv; x[2] = x[2] * inv;
     } else {
         x[0] = 0.0f; x[1] = 0.0f; x[2] = 0.0f;
@@ -444,7 +488,7 @@ __device__ __forceinline__ Attr frag_attr(const DScene& sc, const TriR& r, const
     float b0 = f0 * r.ia, b1 = f1 * r.ia, b2 = f2 * r.ia;
     float pc0 = b0 * s.iw[0], pc1 = b1 * s.iw[1], pc2 = b2 * s.iw[2];
     float S = (pc0 + pc1) + pc2;
-    float iS = 1.0f / S;
+    float iS = rcp_rn(S);
     bool sw = (r.flags & TRI_SWAPPED) != 0u;
     const float* cuv = cu.c;
     float cu0 = cuv[0], cv0 = cuv[1], cu1 = cuv[2], cv1 = cuv[3], cu2 = cuv[4], cv2 = cuv[5];

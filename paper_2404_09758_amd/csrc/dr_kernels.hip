@@ -1639,12 +1639,14 @@ __global__ void __launch_bounds__(256) k_step_b(BatchArgs b) {
 // and read back in between.  Q_i + sum_n s_i^(n) R_g^(n) is the value the
 // fold would leave in Q; it is used as step_group uses Q, and Q, R and K are
 // left zero as the two kernels leave them.
+// q_zero: Q is known to be zero (not read).
 __device__ __forceinline__ void fold_step_group(const DScene& sc, long long g, long long* __restrict__ R,
                                                 const uint32_t* __restrict__ bits, int n_pairs, const float* eps,
                                                 const float* lr, const OptimConst& oc, float bc1, float bc2,
                                                 float* __restrict__ theta, float* __restrict__ m,
                                                 float* __restrict__ v, long long* __restrict__ Q,
-                                                unsigned* __restrict__ K, unsigned long long* __restrict__ stats) {
+                                                unsigned* __restrict__ K, unsigned long long* __restrict__ stats,
+                                                int q_zero) {
     long long r[8];
     bool any = false;
 #pragma unroll
@@ -1656,7 +1658,7 @@ __device__ __forceinline__ void fold_step_group(const DScene& sc, long long g, l
     double D = (oc.averaging == 0) ? (double)kc : (double)n_pairs;
     for_params(sc, g, [&](long long i, int b) {
         float e = eps[b];
-        long long q0 = Q[i];
+        long long q0 = q_zero ? 0ll : Q[i];
         long long acc = 0;
         if (any && e != 0.0f) {
 #pragma unroll
@@ -1706,7 +1708,7 @@ __global__ void __launch_bounds__(256) k_fold_step_b(BatchArgs b) {
     if (t < 1u) t = 1u;                      // Adam steps count from 1
     int ti = (int)min(t, (unsigned)b.n_bc) - 1;
     fold_step_group(S.sc, g, S.R, S.bits, b.n_pairs, S.eps, S.lr, b.oc, b.bc1[ti], b.bc2[ti], (float*)S.theta,
-                    S.m, S.v, S.Q, S.K, b.stats);
+                    S.m, S.v, S.Q, S.K, b.stats, b.q_zero);
 }
 
 // --------------------------------------------------------- launchers --

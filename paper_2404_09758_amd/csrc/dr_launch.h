@@ -159,6 +159,7 @@ struct BatchArgs {
     const float* bc2;
     int n_bc;
     int tile;
+    int q_zero;                  // every scene's Q is known to be zero (the fused step skips reading it)
 };
 
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,

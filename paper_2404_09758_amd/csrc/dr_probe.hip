@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dr.h"
+#include "dr_device.h"
 
 namespace {
 
@@ -44,7 +45,48 @@ __global__ void __launch_bounds__(256) k_atomic_probe(T* buf, unsigned long long
     __hip_atomic_fetch_add(&buf[e], (T)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Every float whose bit pattern lies in [lo, hi] (a grid-stride pass):
+// the fast sequence against the general one, counting the operands where
+// they differ and keeping the least such bit pattern.
+__global__ void __launch_bounds__(256) k_math_probe(int op, unsigned lo, unsigned hi,
+                                                    unsigned long long* __restrict__ bad,
+                                                    unsigned* __restrict__ first) {
+    unsigned long long n = (unsigned long long)hi - lo + 1ull;
+    unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0;
+    unsigned least = 0xFFFFFFFFu;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        unsigned b = lo + (unsigned)i;
+        float x = __uint_as_float(b);
+        float f, g;
+        if (op == DR_PROBE_SQRT) {
+            f = sqrt_rn_fast(x);
+            g = sqrtf(x);
+        } else {
+            f = rcp_rn_fast(x);
+            g = 1.0f / x;
+        }
+        if (__float_as_uint(f) != __float_as_uint(g)) {
+            ++cnt;
+            least = min(least, b);
+        }
+    }
+    if (cnt) {
+        atomicAdd(bad, cnt);
+        atomicMin(first, least);
+    }
+}
+
 }  // namespace
+
+extern "C" dr_status dr_probe_math(int32_t op, uint32_t lo, uint32_t hi, uint64_t* bad, uint32_t* first,
+                                   void* stream) {
+    if (!bad || !first || lo > hi) return DR_E_INVALID;
+    if (op != DR_PROBE_SQRT && op != DR_PROBE_RCP) return DR_E_INVALID;
+    hipLaunchKernelGGL(k_math_probe, dim3(8192), dim3(256), 0, (hipStream_t)stream, (int)op, lo, hi,
+                       (unsigned long long*)bad, first);
+    return hipGetLastError() == hipSuccess ? DR_OK : DR_E_HIP;
+}
 
 extern "C" dr_status dr_probe_atomics(void* buf, int64_t bytes, int32_t width_bits, int32_t pattern, int64_t n_ops,
                                       void* stream) {

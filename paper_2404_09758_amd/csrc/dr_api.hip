@@ -1164,6 +1164,12 @@ extern "C" const char* dr_last_error(const dr_ctx* c) { return c ? c->err.c_str(
 
 // ============================================================== batch ==
 
+// Item groups of a step of a batch of several scenes (see
+// dr_batch::groups); a one-scene batch runs as one group.  Measured: the
+// 64-scene batch 8.7 -> 7.4 ms per step with 4 groups; the one-scene paper
+// step 2.19 -> 2.22 ms with 2 (its setup alone fills the chip).
+#define BATCH_GROUPS 4
+
 struct dr_batch {
     int device = 0;
     hipStream_t stream = nullptr;      // caller's stream
@@ -1181,6 +1187,18 @@ struct dr_batch {
     unsigned long long* stats = nullptr;
     Timer timer;                       // direct launches only (not graph replays)
     bool q_dirty = true;               // Q may hold sums (set at creation and by dr_batch_estimate)
+    // The step's items in groups of about equal tile counts: the setup of
+    // groups 1.. runs on a second stream while the tile kernel works on the
+    // groups before it, filling the chip while the many small scenes of a
+    // batch leave it partly idle.
+    struct Group {
+        long long blk0, nblk;          // setup blocks
+        long long w0, nw;              // tile units
+    };
+    std::vector<Group> groups;
+    hipStream_t astream = nullptr;     // the setups of groups 1..
+    hipEvent_t ev_signs = nullptr;
+    std::vector<hipEvent_t> ev_setup;
 };
 
 static dr_status bfail(dr_batch* b, dr_status s, const std::string& msg) {
@@ -1201,6 +1219,10 @@ static void batch_free(dr_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_signs) (void)hipEventDestroy(b->ev_signs);
+    for (hipEvent_t e : b->ev_setup)
+        if (e) (void)hipEventDestroy(e);
+    if (b->astream) (void)hipStreamDestroy(b->astream);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
     for (void* p : b->allocs)
         if (p) (void)hipFree(p);
@@ -1358,6 +1380,37 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     A.setup_blocks = setup_blk;
     A.group_blocks = group_blk;
     A.total_tiles = tile0;
+    A.unit0 = 0;
+    // items in BATCH_GROUPS groups of about equal tile counts (item order)
+    {
+        const int G = n_scenes == 1 ? 1 : (int)std::min<size_t>(BATCH_GROUPS, hi.size());
+        size_t i = 0;
+        for (int g = 0; g < G && i < hi.size(); ++g) {
+            const long long cut = (g + 1 == G) ? tile0 : tile0 * (g + 1) / G;
+            size_t j = i + 1;
+            while (j < hi.size() && hi[j].tile0 < cut) ++j;
+            if (g + 1 < G && j >= hi.size() && j > i + 1) --j;      // leave items for the later groups
+            dr_batch::Group gr;
+            gr.blk0 = hi[i].setup_blk0;
+            gr.nblk = (j < hi.size() ? hi[j].setup_blk0 : setup_blk) - gr.blk0;
+            gr.w0 = hi[i].tile0;
+            gr.nw = (j < hi.size() ? hi[j].tile0 : tile0) - gr.w0;
+            b->groups.push_back(gr);
+            i = j;
+        }
+        if (b->groups.size() > 1) {
+            bool ok2 = hipStreamCreateWithFlags(&b->astream, hipStreamNonBlocking) == hipSuccess &&
+                       hipEventCreateWithFlags(&b->ev_signs, hipEventDisableTiming) == hipSuccess;
+            b->ev_setup.assign(b->groups.size(), nullptr);
+            for (size_t g = 1; ok2 && g < b->groups.size(); ++g)
+                ok2 = hipEventCreateWithFlags(&b->ev_setup[g], hipEventDisableTiming) == hipSuccess;
+            if (!ok2) {
+                batch_free(b);
+                delete b;
+                return DR_E_HIP;
+            }
+        }
+    }
 
     // Adam bias corrections by step, until both reach 1 in float
     std::vector<float> bc1, bc2;
@@ -1423,20 +1476,45 @@ extern "C" dr_status dr_batch_destroy(dr_batch* b) {
     if (!b) return DR_E_INVALID;
     (void)hipStreamSynchronize(b->stream);
     if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+    if (b->astream) (void)hipStreamSynchronize(b->astream);
     batch_free(b);
     delete b;
     return DR_OK;
 }
 
+// Signs, then per group the setup and the tile launch, then the descent.
+// Untimed, the setups of groups 1.. go to the second stream (ordered after
+// the signs) and each group's tile launch waits for its setup; timed, every
+// launch runs in order on st so that each is bracketed by its own events.
 static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool timed) {
     const BatchArgs& A = b->args;
     Timer off;
     Timer& T = timed ? b->timer : off;
     hipError_t e;
-    if ((e = T.run(st, K_SIGNS, [&] { return launch_batch_signs(st, A); })) != hipSuccess) return e;
-    if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A); })) != hipSuccess) return e;
     const BatchOne* one = b->has_one ? &b->one : nullptr;
-    if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A, one); })) != hipSuccess) return e;
+    if ((e = T.run(st, K_SIGNS, [&] { return launch_batch_signs(st, A); })) != hipSuccess) return e;
+    const size_t G = b->groups.size();
+    if (!timed && G > 1) {
+        if ((e = hipEventRecord(b->ev_signs, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(b->astream, b->ev_signs, 0)) != hipSuccess) return e;
+        for (size_t g = 1; g < G; ++g) {
+            if ((e = launch_batch_setup(b->astream, A, b->groups[g].blk0, b->groups[g].nblk)) != hipSuccess) return e;
+            if ((e = hipEventRecord(b->ev_setup[g], b->astream)) != hipSuccess) return e;
+        }
+        if ((e = launch_batch_setup(st, A, b->groups[0].blk0, b->groups[0].nblk)) != hipSuccess) return e;
+        for (size_t g = 0; g < G; ++g) {
+            if (g > 0 && (e = hipStreamWaitEvent(st, b->ev_setup[g], 0)) != hipSuccess) return e;
+            if ((e = launch_batch_tile(st, A, one, b->groups[g].w0, b->groups[g].nw)) != hipSuccess) return e;
+        }
+    } else {
+        for (size_t g = 0; g < G; ++g) {
+            const auto& gr = b->groups[g];
+            if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A, gr.blk0, gr.nblk); })) != hipSuccess)
+                return e;
+            if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A, one, gr.w0, gr.nw); })) != hipSuccess)
+                return e;
+        }
+    }
     if (descend && A.n_pairs <= 8) {
         // the fold's sums go straight into the update (timed as the step)
         if ((e = T.run(st, K_STEP, [&] { return launch_batch_fold_step(st, A); })) != hipSuccess) return e;

@@ -1517,7 +1517,7 @@ __global__ void __launch_bounds__(256) k_signs_b(BatchArgs b) {
 // Setup of every (item, sign, triangle): each (item, sign) starts on a
 // block boundary.
 __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
-    long long blk = blockIdx.x;
+    long long blk = b.unit0 + blockIdx.x;
     int it = last_le((const char*)&b.items[0].setup_blk0, sizeof(BItem), b.n_items, blk);
     it = __builtin_amdgcn_readfirstlane(it);
     const BItem& I = b.items[it];
@@ -1587,7 +1587,7 @@ __device__ __forceinline__ int unit_item(const BatchArgs& b, long long w) {
 template <int TILE>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b(BatchArgs b) {
     __shared__ TileShared<TILE, 0> S;
-    long long w = xcd_tile(blockIdx.x, gridDim.x);
+    long long w = b.unit0 + xcd_tile(blockIdx.x, gridDim.x);
     if (w >= b.total_tiles) return;
     const BItem& I = b.items[unit_item(b, w)];
     const BScene& Sc = b.scenes[I.scene];
@@ -1600,7 +1600,7 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE 
 template <int TILE>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b1(BatchArgs b, BatchOne one) {
     __shared__ TileShared<TILE, 0> S;
-    long long w = xcd_tile(blockIdx.x, gridDim.x);
+    long long w = b.unit0 + xcd_tile(blockIdx.x, gridDim.x);
     if (w >= b.total_tiles) return;
     const BItem& I = b.items[unit_item(b, w)];
     const BScene& Sc = b.scenes[I.scene];
@@ -1806,22 +1806,28 @@ hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b) {
-    hipLaunchKernelGGL(k_setup_b, dim3((unsigned)b.setup_blocks), dim3(256), 0, st, b);
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, long long blk0, long long nblk) {
+    if (nblk <= 0) return hipSuccess;
+    BatchArgs a = b;
+    a.unit0 = blk0;
+    hipLaunchKernelGGL(k_setup_b, dim3((unsigned)nblk), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one) {
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one, long long w0, long long n) {
+    if (n <= 0) return hipSuccess;
     int tb = (b.tile * b.tile > 256) ? 256 : b.tile * b.tile;
-    unsigned grid = (unsigned)b.total_tiles;
+    unsigned grid = (unsigned)n;
+    BatchArgs a = b;
+    a.unit0 = w0;
     if (one) {
-        if (b.tile == 8) hipLaunchKernelGGL(k_tile_b1<8>, dim3(grid), dim3(tb), 0, st, b, *one);
-        else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b1<16>, dim3(grid), dim3(tb), 0, st, b, *one);
-        else hipLaunchKernelGGL(k_tile_b1<32>, dim3(grid), dim3(tb), 0, st, b, *one);
+        if (a.tile == 8) hipLaunchKernelGGL(k_tile_b1<8>, dim3(grid), dim3(tb), 0, st, a, *one);
+        else if (a.tile == 16) hipLaunchKernelGGL(k_tile_b1<16>, dim3(grid), dim3(tb), 0, st, a, *one);
+        else hipLaunchKernelGGL(k_tile_b1<32>, dim3(grid), dim3(tb), 0, st, a, *one);
     } else {
-        if (b.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, b);
-        else if (b.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, b);
-        else hipLaunchKernelGGL(k_tile_b<32>, dim3(grid), dim3(tb), 0, st, b);
+        if (a.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, a);
+        else if (a.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, a);
+        else hipLaunchKernelGGL(k_tile_b<32>, dim3(grid), dim3(tb), 0, st, a);
     }
     return hipGetLastError();
 }

@@ -160,6 +160,7 @@ struct BatchArgs {
     int n_bc;
     int tile;
     int q_zero;                  // every scene's Q is known to be zero (the fused step skips reading it)
+    long long unit0;             // setup and tile launches: the first block / tile unit of the launch
 };
 
 hipError_t launch_signs(hipStream_t st, unsigned long long seed, unsigned step, unsigned pair0, unsigned scene,
@@ -177,7 +178,8 @@ hipError_t launch_zero64(hipStream_t st, long long* p, int n);
 hipError_t launch_step(hipStream_t st, const StepArgs& a);
 
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);
-hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b);
+// setup blocks [blk0, blk0 + nblk) of the batch's setup grid
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, long long blk0, long long nblk);
 // A one-scene batch's scene constants and views, passed to the tile launch
 // by value.
 struct BatchOne {
@@ -187,7 +189,8 @@ struct BatchOne {
 
 // one: non-null for a one-scene batch (the batch's view table is then the
 // scene's views).
-hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one);
+// tile units [w0, w0 + n) of the batch
+hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne* one, long long w0, long long n);
 hipError_t launch_batch_fold(hipStream_t st, const BatchArgs& b);
 hipError_t launch_batch_step(hipStream_t st, const BatchArgs& b);
 // fold and step in one launch (at most 8 pairs)

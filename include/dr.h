@@ -110,8 +110,10 @@ typedef struct {
 } dr_view;
 
 /* Launch shape.  Raster tiles are tile_px (8, 16 or 32) pixels square,
- * each with a bin of bin_capacity triangles; a tile whose bin overflows
- * falls back to testing every triangle.  items_per_launch is the number of
+ * each with a bin of bin_capacity triangles; the entries of a bin past its
+ * capacity go to a spill list of the render (8192 entries), which the
+ * overflowing tile reads after its bin; only when that list is full does
+ * the tile test every triangle of the render.  items_per_launch is the number of
  * (pair, view) items one raster launch covers: 1 = one launch per item
  * ("plain"), 0 = every item of the call in one launch ("batched").
  * Results never depend on these values. */
@@ -143,6 +145,9 @@ typedef struct {
     uint64_t nonfinite;          /* NaN differences dropped; non-finite
                                     gradients skipped by dr_step              */
     uint64_t max_bin;            /* largest bin occupancy seen (triangles)    */
+    uint64_t full_scans;         /* overflowing bins whose render's spill list
+                                    (8192 entries) was full, so the tile tested
+                                    every triangle of the render              */
 } dr_stats_t;
 
 /* Create a context for one scene on the current HIP device; stream is a
@@ -178,8 +183,8 @@ dr_status dr_subdivide(const int32_t* tri, const float* corner_uv, int32_t n_ver
                        int32_t* cols, float* w);
 
 /* Adaptive bin capacity (default on): after an estimate whose largest tile
- * bin exceeded bin_capacity (an overflowing tile falls back to testing
- * every triangle, exact but slow), a later dr_estimate_grad* call raises
+ * bin exceeded bin_capacity (an overflowing tile also reads the render's
+ * spill list, exact but slower), a later dr_estimate_grad* call raises
  * the capacity to the next power of two above 1.5x that bin (at most 2^16),
  * reallocating the bins once.  The figure is read back asynchronously, so
  * the raise may come one call later.  Results never depend on it.

@@ -55,7 +55,7 @@ class Optim(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("tile_overflows", C.c_uint64), ("saturations", C.c_uint64), ("nonfinite", C.c_uint64),
-                ("max_bin", C.c_uint64)]
+                ("max_bin", C.c_uint64), ("full_scans", C.c_uint64)]
 
 
 class BatchScene(C.Structure):

@@ -299,7 +299,7 @@ class Context:
         s = L.Stats()
         self._call("dr_stats", C.byref(s))
         return {"tile_overflows": s.tile_overflows, "saturations": s.saturations, "nonfinite": s.nonfinite,
-                "max_bin": s.max_bin}
+                "max_bin": s.max_bin, "full_scans": s.full_scans}
 
     def reset_stats(self):
         self._call("dr_reset_stats")

@@ -124,4 +124,4 @@ class Batch:
         s = L.Stats()
         self._call("dr_batch_stats", C.byref(s))
         return {"tile_overflows": s.tile_overflows, "saturations": s.saturations, "nonfinite": s.nonfinite,
-                "max_bin": s.max_bin}
+                "max_bin": s.max_bin, "full_scans": s.full_scans}

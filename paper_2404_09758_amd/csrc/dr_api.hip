@@ -103,6 +103,10 @@ struct dr_ctx {
     unsigned* bins = nullptr;
     long long tile_slots = 0;       // slots * max_tiles allocated
     long long bin_entries = 0;      // tile_slots * cap allocated
+    unsigned* spn = nullptr;        // [slots, 2] spill counters
+    long long spn_words = 0;
+    unsigned long long* spill = nullptr;   // [slots, SPILL_CAP] spill lists
+    long long spill_entries = 0;
     long long* R = nullptr;
     long long R_pairs = 0;
     uint32_t* bits = nullptr;
@@ -179,6 +183,10 @@ static dr_status ensure_raster(dr_ctx* c, long long slots, int max_tiles) {
     if (s) return s;
     if (slots * c->sc.n_tris > c->rec_slots) c->rec_slots = slots * c->sc.n_tris;
     s = grow(c, &c->counts, &c->tile_slots, slots * (long long)max_tiles, sizeof(unsigned), true);
+    if (s) return s;
+    s = grow(c, &c->spn, &c->spn_words, 2 * slots, sizeof(unsigned), true);
+    if (s) return s;
+    s = grow(c, &c->spill, &c->spill_entries, slots * (long long)SPILL_CAP, sizeof(unsigned long long), false);
     if (s) return s;
     return grow(c, &c->bins, &c->bin_entries, slots * (long long)max_tiles * c->tune.bin_capacity,
                 sizeof(unsigned), false);
@@ -443,7 +451,7 @@ extern "C" dr_status dr_destroy(dr_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->h_seen) (void)hipHostFree(c->h_seen);
     if (c->ev_seen) (void)hipEventDestroy(c->ev_seen);
-    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->R, c->bits, c->stats, c->partials,
+    void* ptrs[] = {c->recR, c->recS, c->counts, c->bins, c->spn, c->spill, c->R, c->bits, c->stats, c->partials,
                     c->qtot, c->tri_rowptr, c->tri_cols, c->fpos};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -553,6 +561,8 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     sa.recS = c->recS;
     sa.counts = c->counts;
     sa.bins = c->bins;
+    sa.spn = c->spn;
+    sa.spill = c->spill;
     s = tessellate(c, theta, dp, 1, 1, sg, sg, &sa.fpos);
     if (s) return s;
     HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, 1); }));
@@ -573,6 +583,8 @@ extern "C" dr_status dr_render(dr_ctx* c, const float* theta, const dr_view* vie
     ta.recS = c->recS;
     ta.counts = c->counts;
     ta.bins = c->bins;
+    ta.spn = c->spn;
+    ta.spill = c->spill;
     ta.stats = c->stats;
     ta.out_rgb = rgb;
     ta.out_id = id;
@@ -626,6 +638,8 @@ struct EstScratch {
     TriS* recS = nullptr;
     unsigned* counts = nullptr;
     unsigned* bins = nullptr;
+    unsigned* spn = nullptr;
+    unsigned long long* spill = nullptr;
     long long* R = nullptr;
     long long* qtot = nullptr;
     float* fpos = nullptr;
@@ -695,6 +709,8 @@ static dr_status estimate_scratch_ctx(dr_ctx* c, const EstPlan& pl, int32_t n_pa
     x.recS = c->recS;
     x.counts = c->counts;
     x.bins = c->bins;
+    x.spn = c->spn;
+    x.spill = c->spill;
     x.R = c->R;
     x.qtot = c->qtot;
     x.fpos = c->fpos;
@@ -739,6 +755,8 @@ static dr_status estimate_launch(dr_ctx* c, const EstPlan& pl, const float* thet
     sa.recS = x.recS;
     sa.counts = x.counts;
     sa.bins = x.bins;
+    sa.spn = x.spn;
+    sa.spill = x.spill;
     TileArgs ta;
     std::memset(&ta, 0, sizeof(ta));
     ta.sc = c->sc;
@@ -755,6 +773,8 @@ static dr_status estimate_launch(dr_ctx* c, const EstPlan& pl, const float* thet
     ta.recS = x.recS;
     ta.counts = x.counts;
     ta.bins = x.bins;
+    ta.spn = x.spn;
+    ta.spill = x.spill;
     ta.stats = c->stats;
     ta.targets = targets;
     ta.img_grad = image ? 1 : 0;
@@ -889,12 +909,14 @@ static unsigned long long static_layout(const dr_ctx* c, const EstPlan& pl, int3
     };
     const unsigned long long bin_slots = slots * (unsigned long long)pl.max_tiles;
     unsigned long long o_counts = take(bin_slots * sizeof(unsigned));
+    unsigned long long o_spn = take(slots * 2ull * sizeof(unsigned));
     unsigned long long o_R = take((unsigned long long)n_pairs * (unsigned long long)sc.G * sizeof(long long));
     if (zero_bytes) *zero_bytes = off;
     unsigned long long o_bits = take(((unsigned long long)n_pairs * (unsigned long long)sc.words + 1ull) * 4ull);
     unsigned long long o_recR = take(slots * (unsigned long long)sc.n_tris * sizeof(TriR));
     unsigned long long o_recS = take(slots * (unsigned long long)sc.n_tris * sizeof(TriS));
     unsigned long long o_bins = take(bin_slots * cap * sizeof(unsigned));
+    unsigned long long o_spill = take(slots * (unsigned long long)SPILL_CAP * sizeof(unsigned long long));
     unsigned long long o_fpos = 0;
     if (sc.n_ctrl > 0) o_fpos = take((unsigned long long)n_pairs * 2ull * (unsigned long long)sc.n_verts * 12ull);
     if (base && x) {
@@ -904,6 +926,8 @@ static unsigned long long static_layout(const dr_ctx* c, const EstPlan& pl, int3
         x->recR = (TriR*)(base + o_recR);
         x->recS = (TriS*)(base + o_recS);
         x->bins = (unsigned*)(base + o_bins);
+        x->spn = (unsigned*)(base + o_spn);
+        x->spill = (unsigned long long*)(base + o_spill);
         x->fpos = sc.n_ctrl > 0 ? (float*)(base + o_fpos) : nullptr;
         x->qtot = nullptr;
         x->cap = (int)cap;
@@ -993,6 +1017,8 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     sa.recS = c->recS;
     sa.counts = c->counts;
     sa.bins = c->bins;
+    sa.spn = c->spn;
+    sa.spill = c->spill;
     s = tessellate(c, theta, dp, 1, 1, 1.0f, 1.0f, &sa.fpos);
     if (s) return s;
     HIPCHK(c, c->timer.run(c->stream, K_SETUP, [&] { return launch_setup(c->stream, sa, n_views); }));
@@ -1012,6 +1038,8 @@ extern "C" dr_status dr_loss(dr_ctx* c, const float* theta, const dr_view* views
     ta.recS = c->recS;
     ta.counts = c->counts;
     ta.bins = c->bins;
+    ta.spn = c->spn;
+    ta.spill = c->spill;
     ta.stats = c->stats;
     ta.targets = targets;
     ta.partials = c->partials;
@@ -1125,6 +1153,7 @@ extern "C" dr_status dr_stats(dr_ctx* c, dr_stats_t* out) {
     out->saturations = h[ST_SATURATIONS];
     out->nonfinite = h[ST_NONFINITE];
     out->max_bin = h[ST_MAX_BIN];
+    out->full_scans = h[ST_FULL_SCANS];
     return DR_OK;
 }
 
@@ -1299,7 +1328,7 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
         return px;
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-    long long sign_blk = 0, group_blk = 0, rec = 0, cnt = 0, bin = 0, setup_blk = 0, tile0 = 0;
+    long long sign_blk = 0, group_blk = 0, rec = 0, cnt = 0, bin = 0, sp = 0, setup_blk = 0, tile0 = 0;
     std::vector<long long> bits_off(n_scenes), R_off(n_scenes);
     long long bits_total = 0, R_total = 0;
     for (int i = 0; i < n_scenes; ++i) {
@@ -1363,6 +1392,8 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
                 cnt += 2 * tiles;
                 I.bin_off = bin;
                 bin += 2 * tiles * cap;
+                I.sp_off = sp;
+                sp += 2;
                 I.setup_blk0 = setup_blk;
                 setup_blk += 2 * (((long long)S.sc.n_tris + 255) >> 8);
                 I.tile0 = tile0;
@@ -1433,6 +1464,8 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
     if ((st = balloc(b, &bits, (size_t)bits_total + 1, false)) || (st = balloc(b, &R, (size_t)R_total, true)) ||
         (st = balloc(b, &A.recR, (size_t)rec, false)) || (st = balloc(b, &A.recS, (size_t)rec, false)) ||
         (st = balloc(b, &A.counts, (size_t)cnt, true)) || (st = balloc(b, &A.bins, (size_t)bin, false)) ||
+        (st = balloc(b, &A.spn, (size_t)sp * 2, true)) ||
+        (st = balloc(b, &A.spill, (size_t)sp * SPILL_CAP, false)) ||
         (st = balloc(b, &dsc, hs.size(), false)) || (st = balloc(b, &dvw, hv.size(), false)) ||
         (st = balloc(b, &dit, hi.size(), false)) || (st = balloc(b, &dbc1, bc1.size(), false)) ||
         (st = balloc(b, &dbc2, bc2.size(), false)) || (st = balloc(b, &dstep, 1, false)) ||
@@ -1467,6 +1500,12 @@ extern "C" dr_status dr_batch_create(dr_batch** out, const dr_batch_scene* scene
         b->has_one = true;
         b->one.sc = hs[0].sc;
         for (size_t v = 0; v < hv.size(); ++v) b->one.views[v] = hv[v];
+        // items are numbered (pair, view): the tile launch walks them pair-interleaved
+        b->one.n_views = (int)hv.size();
+        b->one.il_pairs = n_pairs;
+        b->one.tsum[0] = 0;
+        for (size_t v = 0; v < hv.size(); ++v)
+            b->one.tsum[v + 1] = b->one.tsum[v] + (long long)hv[v].tiles_x * hv[v].tiles_y;
     }
     *out = b;
     return DR_OK;
@@ -1615,6 +1654,7 @@ extern "C" dr_status dr_batch_stats(dr_batch* b, dr_stats_t* out) {
     out->saturations = h[ST_SATURATIONS];
     out->nonfinite = h[ST_NONFINITE];
     out->max_bin = h[ST_MAX_BIN];
+    out->full_scans = h[ST_FULL_SCANS];
     return DR_OK;
 }
 

@@ -60,6 +60,7 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
                                           TriR* __restrict__ recR, TriS* __restrict__ recS,
                                           unsigned* __restrict__ counts,
                                           unsigned* __restrict__ bins, int tile_px, int cap,
+                                          unsigned* __restrict__ spn, unsigned long long* __restrict__ spill,
                                           const float* __restrict__ fpos) {
     int vid[3];
     float p[9];
@@ -166,9 +167,23 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
         unsigned base = 0u;
         if (has && my_leader == lane) base = atomicAdd(&counts[tile], group);
         base = __shfl(base, my_leader);
-        if (has) {
-            unsigned k = base + rank;
-            if (k < (unsigned)cap) bins[(long long)tile * cap + k] = (unsigned)t;
+        const unsigned k = base + rank;
+        if (has && k < (unsigned)cap) bins[(long long)tile * cap + k] = (unsigned)t;
+        // entries past the capacity go to the render's spill list (the
+        // first of a tile also counts the tile as overflowing)
+        const bool sp = has && k >= (unsigned)cap && spill != nullptr;
+        const unsigned long long ms = __ballot(sp);
+        if (ms) {
+            const int first = __ffsll((long long)ms) - 1;
+            unsigned j0 = 0u;
+            if (lane == first) j0 = atomicAdd(&spn[0], (unsigned)__popcll(ms));
+            j0 = __shfl(j0, first);
+            if (sp) {
+                const unsigned j = j0 + __builtin_amdgcn_mbcnt_hi((unsigned)(ms >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)ms, 0u));
+                if (j < SPILL_CAP) spill[j] = ((unsigned long long)(unsigned)tile << 32) | (unsigned)t;
+                if (k == (unsigned)cap) atomicAdd(&spn[1], 1u);
+            }
         }
     }
 }
@@ -186,7 +201,8 @@ __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
     setup_tri(sc, a.views.v[view], a.theta, pb, a.pert.eps[0], a.sgn[s], t, a.recR + (long long)slot * sc.n_tris,
               a.recS + (long long)slot * sc.n_tris,
               a.counts + (long long)slot * a.max_tiles, a.bins + (long long)slot * a.max_tiles * a.cap, a.tile,
-              a.cap, fpos);
+              a.cap, a.spn ? a.spn + 2ll * slot : nullptr, a.spill ? a.spill + (long long)slot * SPILL_CAP : nullptr,
+              fpos);
 }
 
 // Tessellated vertex positions of a subdivision surface for every (pair,
@@ -579,6 +595,66 @@ __device__ __forceinline__ void raster_scan(const TriR* __restrict__ R, int n_tr
     }
 }
 
+// The spill entries of an overflowing bin: the render's spill list read 64
+// entries at a time, the triangles that name this tile packed to the low
+// lanes and rasterised as one batch.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_spill(const TriR* __restrict__ R, const unsigned long long* __restrict__ spill,
+                                             unsigned ns, int tile, int wave, int nw, int lane, int px0, int py0,
+                                             int cx1, int cy1, unsigned long long* key, int L, RasterStage* stage) {
+    for (unsigned j0 = (unsigned)wave * 64u; j0 < ns; j0 += 64u * (unsigned)nw) {
+        const unsigned j = j0 + (unsigned)lane;
+        bool hit = false;
+        unsigned t = 0u;
+        if (j < ns) {
+            const unsigned long long e = gload(&spill[j]);
+            hit = (unsigned)(e >> 32) == (unsigned)tile;
+            t = (unsigned)e;
+        }
+        unsigned long long m = __ballot(hit);
+        if (m == 0ull) continue;
+        int n = __popcll(m);
+        int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        int dst = hit ? below : n + (lane - below);
+        unsigned mine = (unsigned)__builtin_amdgcn_ds_permute(dst * 4, (int)t);
+        raster_group<TILE, DEEP>(R, mine, (unsigned)n, px0, py0, cx1, cy1, lane, key, L, stage);
+    }
+}
+
+// Every triangle of one render that may cover the tile: its bin of cnt
+// entries; for a bin past its capacity the full bin and the tile's entries
+// of the render's spill list, or, when that list ran out of room (or there
+// is none), every triangle of the render.  `note`: this wave counts a
+// full scan in the statistics.
+template <int TILE, bool DEEP>
+__device__ __forceinline__ void raster_render(const TriR* __restrict__ R, const unsigned* __restrict__ bin,
+                                              unsigned cnt, unsigned cap, const unsigned* spn,
+                                              const unsigned long long* __restrict__ spill, int n_tris, int tile,
+                                              int wave, int nw, int lane, int px0, int py0, int cx1, int cy1,
+                                              unsigned long long* key, int L, RasterStage* stage,
+                                              unsigned long long* stats, bool note) {
+    if (cnt <= cap) {
+        raster_bin<TILE, DEEP>(bin, cnt, R, wave, nw, lane, px0, py0, cx1, cy1, key, L, stage);
+        return;
+    }
+    const unsigned ns = spn ? gload(&spn[0]) : 0xFFFFFFFFu;
+    if (ns <= SPILL_CAP) {
+        raster_bin<TILE, DEEP>(bin, cap, R, wave, nw, lane, px0, py0, cx1, cy1, key, L, stage);
+        raster_spill<TILE, DEEP>(R, spill, ns, tile, wave, nw, lane, px0, py0, cx1, cy1, key, L, stage);
+    } else {
+        if (note && lane == 0) atomicAdd(&stats[ST_FULL_SCANS], 1ull);
+        raster_scan<TILE, DEEP>(R, n_tris, wave, nw, lane, px0, py0, cx1, cy1, key, L, stage);
+    }
+}
+
+// After the tile's raster: leave its bin empty for the next use, and the
+// last overflowing tile of the render empties the render's spill list.
+__device__ __forceinline__ void release_bin(unsigned* counts, int tile, unsigned cap, unsigned* spn) {
+    const unsigned c = counts[tile];
+    counts[tile] = 0u;
+    if (c > cap && spn != nullptr && atomicSub(&spn[1], 1u) == 1u) spn[0] = 0u;
+}
+
 // ------------------------------------------------ tile-local aggregation --
 //
 // Contributions are summed per group inside the workgroup before they reach
@@ -711,6 +787,8 @@ struct TileJob {
     const TriS* recS[2];
     unsigned* counts[2];                 // bin counters of each sign (index = tile)
     const unsigned* bins[2];             // bin entries of each sign (tile * cap + k)
+    unsigned* spn[2];                    // spill counters of each sign, or null
+    const unsigned long long* spill[2];  // spill lists of each sign
     int cap;
     int tile;
     unsigned long long* stats;
@@ -785,20 +863,20 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
             const TriR* __restrict__ R = s1 ? J.recR[NS - 1] : J.recR[0];
             const unsigned* bins = s1 ? J.bins[NS - 1] : J.bins[0];
             unsigned* counts = s1 ? J.counts[NS - 1] : J.counts[0];
+            const unsigned* spn = s1 ? J.spn[NS - 1] : J.spn[0];
+            const unsigned long long* spill = s1 ? J.spill[NS - 1] : J.spill[0];
             unsigned long long* key = s1 ? S.key[NS - 1] : S.key[0];
             unsigned cnt = counts[J.tile];
             if (wv == 0 && lane == 0) note_bin(J.stats, cnt, (unsigned)J.cap);
-            if (cnt <= (unsigned)J.cap)
-                raster_bin<TILE, false>(bins + (long long)J.tile * J.cap, cnt, R, wv, NWS, lane, px0, py0, cx1, cy1,
-                                        key, 1, &S.u.stage[wave]);
-            else
-                raster_scan<TILE, false>(R, sc.n_tris, wv, NWS, lane, px0, py0, cx1, cy1, key, 1, &S.u.stage[wave]);
+            raster_render<TILE, false>(R, bins + (long long)J.tile * J.cap, cnt, (unsigned)J.cap, spn, spill,
+                                       sc.n_tris, J.tile, wv, NWS, lane, px0, py0, cx1, cy1, key, 1,
+                                       &S.u.stage[wave], J.stats, wv == 0);
         }
     }
     __syncthreads();
     if (tid < NS) {                              // leave the bins empty for the next use
-        unsigned* counts = (NS == 2 && tid == 1) ? J.counts[NS - 1] : J.counts[0];
-        counts[J.tile] = 0u;
+        const bool s1 = NS == 2 && tid == 1;
+        release_bin(s1 ? J.counts[NS - 1] : J.counts[0], J.tile, (unsigned)J.cap, s1 ? J.spn[NS - 1] : J.spn[0]);
     }
     if constexpr (MODE == 0) {
         // the stages are done with: the group table takes their place
@@ -1069,16 +1147,14 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         unsigned cnt = J.counts[s][J.tile];
         if (tid == 0) note_bin(J.stats, cnt, (unsigned)J.cap);
         const TriR* __restrict__ R = J.recR[s];
-        if (cnt <= (unsigned)J.cap)
-            raster_bin<TILE, true>(J.bins[s] + (long long)J.tile * J.cap, cnt, R, wave, NW, lane, px0, py0, cx1, cy1,
-                                   S.key[s], L, nullptr);
-        else
-            raster_scan<TILE, true>(R, sc.n_tris, wave, NW, lane, px0, py0, cx1, cy1, S.key[s], L, nullptr);
+        raster_render<TILE, true>(R, J.bins[s] + (long long)J.tile * J.cap, cnt, (unsigned)J.cap, J.spn[s],
+                                  J.spill[s], sc.n_tris, J.tile, wave, NW, lane, px0, py0, cx1, cy1, S.key[s], L,
+                                  nullptr, J.stats, wave == 0);
     }
     __syncthreads();
     if (tid == 0) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) J.counts[s][J.tile] = 0u;
+        for (int s = 0; s < NS; ++s) release_bin(J.counts[s], J.tile, (unsigned)J.cap, J.spn[s]);
     }
 
     int local = tid;
@@ -1281,6 +1357,8 @@ k_tile(TileArgs a) {
         J.recS[s] = a.recS + (long long)slot * sc.n_tris;
         J.counts[s] = a.counts + (long long)slot * a.max_tiles;
         J.bins[s] = a.bins + (long long)slot * a.max_tiles * a.cap;
+        J.spn[s] = a.spn ? a.spn + 2ll * slot : nullptr;
+        J.spill[s] = a.spill ? a.spill + (long long)slot * SPILL_CAP : nullptr;
     }
     J.cap = a.cap;
     J.tile = tile;
@@ -1533,7 +1611,8 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
     setup_tri(sc, vw, S.theta, S.bits + (long long)I.pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t,
               b.recR + I.rec_off + (long long)s * sc.n_tris, b.recS + I.rec_off + (long long)s * sc.n_tris,
               b.counts + I.cnt_off + (long long)s * tiles,
-              b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap, nullptr);
+              b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap, b.spn + 2 * (I.sp_off + s),
+              b.spill + (I.sp_off + s) * SPILL_CAP, nullptr);
 }
 
 // Raster / shade / scatter of every (scene, pair, view, tile) unit in one
@@ -1559,6 +1638,8 @@ __device__ __forceinline__ void tile_b_unit(const BatchArgs& b, const BItem& I, 
         J.recS[s] = b.recS + I.rec_off + (long long)s * sc.n_tris;
         J.counts[s] = b.counts + I.cnt_off + (long long)s * tiles;
         J.bins[s] = b.bins + I.bin_off + (long long)s * tiles * I.cap;
+        J.spn[s] = b.spn + 2 * (I.sp_off + s);
+        J.spill[s] = b.spill + (I.sp_off + s) * SPILL_CAP;
     }
     J.cap = I.cap;
     J.tile = (int)(w - I.tile0);
@@ -1597,11 +1678,25 @@ __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE 
 // The same launch for a one-scene batch, with the scene's constants and
 // views in the kernel arguments: the body reads them with scalar loads
 // instead of vector loads that compete with the texel reads.
+// Unit of position L of a one-scene launch in (view, tile, pair) order.
+// The units of the pairs of one tile then follow each other, so they run
+// at about the same time on one XCD and share its L2 for what they have in
+// common: the texels and target pixels of the tile.
+__device__ __forceinline__ long long pair_interleaved(const BatchOne& one, long long L) {
+    const long long P = one.il_pairs;
+    int v = 0;
+    while (v + 1 < one.n_views && L >= P * one.tsum[v + 1]) ++v;
+    const unsigned r = (unsigned)(L - P * one.tsum[v]);
+    const unsigned t = r / (unsigned)P, p = r - t * (unsigned)P;
+    return (long long)p * one.tsum[one.n_views] + one.tsum[v] + t;
+}
+
 template <int TILE>
 __global__ void __launch_bounds__((TILE * TILE > 256) ? 256 : TILE * TILE, TILE > 16 ? 1 : TILE_MIN_WAVES) k_tile_b1(BatchArgs b, BatchOne one) {
     __shared__ TileShared<TILE, 0> S;
     long long w = b.unit0 + xcd_tile(blockIdx.x, gridDim.x);
     if (w >= b.total_tiles) return;
+    if (one.il_pairs > 1) w = pair_interleaved(one, w);
     const BItem& I = b.items[unit_item(b, w)];
     const BScene& Sc = b.scenes[I.scene];
     tile_b_unit<TILE>(b, I, Sc, one.sc, one.views[I.view], w, S);
@@ -1821,9 +1916,13 @@ hipError_t launch_batch_tile(hipStream_t st, const BatchArgs& b, const BatchOne*
     BatchArgs a = b;
     a.unit0 = w0;
     if (one) {
-        if (a.tile == 8) hipLaunchKernelGGL(k_tile_b1<8>, dim3(grid), dim3(tb), 0, st, a, *one);
-        else if (a.tile == 16) hipLaunchKernelGGL(k_tile_b1<16>, dim3(grid), dim3(tb), 0, st, a, *one);
-        else hipLaunchKernelGGL(k_tile_b1<32>, dim3(grid), dim3(tb), 0, st, a, *one);
+        // the interleaved order is a permutation of all units: a launch of
+        // part of them keeps unit order
+        BatchOne o = *one;
+        if (w0 != 0 || n != b.total_tiles) o.il_pairs = 1;
+        if (a.tile == 8) hipLaunchKernelGGL(k_tile_b1<8>, dim3(grid), dim3(tb), 0, st, a, o);
+        else if (a.tile == 16) hipLaunchKernelGGL(k_tile_b1<16>, dim3(grid), dim3(tb), 0, st, a, o);
+        else hipLaunchKernelGGL(k_tile_b1<32>, dim3(grid), dim3(tb), 0, st, a, o);
     } else {
         if (a.tile == 8) hipLaunchKernelGGL(k_tile_b<8>, dim3(grid), dim3(tb), 0, st, a);
         else if (a.tile == 16) hipLaunchKernelGGL(k_tile_b<16>, dim3(grid), dim3(tb), 0, st, a);

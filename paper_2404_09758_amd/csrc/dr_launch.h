@@ -10,7 +10,13 @@
 #define ST_NONFINITE 2
 #define ST_BAD_INDEX 3
 #define ST_MAX_BIN 4
+#define ST_FULL_SCANS 5       // overflowing (tile, render) bins whose render's spill list was full
 #define ST_COUNT 8
+
+// Spill list of one render: entries (tile << 32 | triangle) of bins past
+// their capacity, and two counters: [0] entries appended, [1] overflowing
+// tiles not yet rasterised.  The last of those tiles empties the list.
+#define SPILL_CAP 8192
 
 // ------------------------------------------------------- single scene --
 
@@ -30,6 +36,8 @@ struct SetupArgs {
     TriS* recS;
     unsigned* counts;
     unsigned* bins;
+    unsigned* spn;                   // [slots, 2] spill counters, or null (no spill lists)
+    unsigned long long* spill;       // [slots, SPILL_CAP]
     const float* fpos;      // subdivision surface: [pairs, nsign, n_verts, 3] positions, else null
 };
 
@@ -48,6 +56,8 @@ struct TileArgs {
     const TriS* recS;
     unsigned* counts;
     const unsigned* bins;
+    unsigned* spn;
+    const unsigned long long* spill;
     unsigned long long* stats;
     // estimate mode
     const float* targets;            // target images, or dL/dI in the image form
@@ -135,6 +145,7 @@ struct BItem {
     long long rec_off;           // records of sign 0 (sign 1 at + n_tris)
     long long cnt_off;           // bin counters of sign 0 (sign 1 at + tiles)
     long long bin_off;           // bin entries of sign 0 (sign 1 at + tiles * cap)
+    long long sp_off;            // spill list of sign 0 (sign 1 at + 1)
     long long setup_blk0;        // first block of this item in the setup launch
     long long tile0;             // first tile unit of this item in the tile launch
 };
@@ -153,6 +164,8 @@ struct BatchArgs {
     TriS* recS;
     unsigned* counts;
     unsigned* bins;
+    unsigned* spn;               // [2 items, 2] spill counters
+    unsigned long long* spill;   // [2 items, SPILL_CAP]
     unsigned long long* stats;
     OptimConst oc;
     const float* bc1;            // Adam bias corrections by step, [n_bc]
@@ -185,6 +198,12 @@ hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, long long blk0
 struct BatchOne {
     DScene sc;
     DView views[DRD_MAX_VIEWS];
+    int n_views;
+    // Tile units in pair-interleaved order: the launch walks (view, tile,
+    // pair) while the units are numbered (pair, view, tile); tsum[v] is the
+    // number of tiles of views 0 .. v-1.  il_pairs = 1 keeps unit order.
+    int il_pairs;
+    long long tsum[DRD_MAX_VIEWS + 1];
 };
 
 // one: non-null for a one-scene batch (the batch's view table is then the

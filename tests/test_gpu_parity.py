@@ -601,3 +601,88 @@ def test_texel_signs_at_the_end_of_the_parameter_vector(shading, shapes):
     bt = batch.Batch([sc], pairs, DEV, tile_px=8, seed=seed, first_step=step, targets=[[dev(t) for t in tg]])
     bt.estimate()
     assert np.array_equal(host(bt.K[0]).view(np.uint32), Ko) and np.array_equal(host(bt.Q[0]), Qo)
+
+
+# ------------------------------------------------------- overflowing bins --
+#
+# A bin past its capacity must not lose triangles (Sec. 4.4 "Opaque
+# geometry": every triangle covering a pixel takes part in its depth test).
+# Entries past the capacity go to the render's spill list, which the
+# overflowing tile reads after its bin; when more than 8192 entries of one
+# render spill, the overflowing tiles test every triangle instead.
+
+SPILL_CAP = 8192
+
+
+def overflow_scene(big):
+    if big:   # 20480 triangles on 128^2 px: with capacity 1 far more entries spill than the list holds
+        return H.sphere_scene(32, 0, res=(128, 128), shading=S.SHADING_LAMBERT, tex_shapes=((64, 64, 3),),
+                              seed=8, views=1)
+    return scene_by_name("lambert")
+
+
+def spilled_entries(sc, tile, cap):
+    """Bin entries past the capacity, per view, from the unperturbed projection."""
+    return [int(np.maximum(H.tile_bin_counts(sc, v, tile)[0] - cap, 0).sum()) for v in sc.views]
+
+
+@pytest.mark.parametrize("big,tile,cap", [(False, 16, 4), (False, 8, 1), (True, 32, 1)])
+def test_overflowing_bins_spill_or_scan_bit_exact(big, tile, cap):
+    sc = overflow_scene(big)
+    spilled = spilled_entries(sc, tile, cap)
+    print(f"[spill] big={big} tile {tile} cap {cap} spilled per view {spilled}", flush=True)
+    if big:
+        assert min(spilled) > 2 * SPILL_CAP
+    else:
+        assert 0 < max(spilled) < SPILL_CAP // 4
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    seed, step, pairs = 77, 1, 2
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, seed, step, pairs, sc.eps)
+    ctx = api.Context(sc, DEV, tuning=(tile, cap, 1))
+    ctx.set_adaptive_bins(False)
+    for call in range(2):                        # the first call leaves the spill lists empty
+        Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], seed, step, pairs, sc.eps)
+        Qg, Kg = host(Q), host(K).view(np.uint32)
+        assert np.array_equal(Kg, Ko), f"call {call}: K differs at {np.nonzero(Kg != Ko)[0][:10]}"
+        assert np.array_equal(Qg, Qo), f"call {call}: Q differs at {np.nonzero(Qg != Qo)[0][:10]}"
+    rgb_o, id_o, uv_o = o.render(theta, sc.views[0])
+    rgb, ids, uv = ctx.render(dev(theta), sc.views[0])
+    assert np.array_equal(host(ids).view(np.uint32), id_o)
+    assert np.array_equal(host(rgb), rgb_o) and np.array_equal(host(uv), uv_o)
+    gs = ctx.stats()
+    assert gs["tile_overflows"] > 0
+    assert (gs["full_scans"] > 0) == big, gs
+
+
+@pytest.mark.parametrize("big", [False, True])
+def test_overflowing_bins_batched_graph_bit_exact(big):
+    sc = overflow_scene(big)
+    tile, cap = (16, 2) if not big else (32, 1)
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    seed, step, pairs = 31, 1, 2
+    bt = batch.Batch([sc], pairs, DEV, tile_px=tile, seed=seed, first_step=step,
+                     targets=[[dev(t) for t in tg]], kind=api.SGD, bin_capacities=[cap])
+    theta0 = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta0, sc.views, tg, seed, step, pairs, sc.eps)
+    for call in range(2):
+        bt.estimate()
+        assert np.array_equal(host(bt.K[0]).view(np.uint32), Ko), f"call {call}"
+        assert np.array_equal(host(bt.Q[0]), Qo), f"call {call}"
+        bt.Q[0].zero_()
+        bt.K[0].zero_()
+    # two graph steps equal two plain steps
+    ctx = api.Context(sc, DEV, tuning=(tile, cap, 1))
+    ctx.set_adaptive_bins(False)
+    th, m, v = bt.theta[0].clone(), bt.m[0].clone(), bt.v[0].clone()
+    for t in range(step, step + 2):
+        bt.step(use_graph=True)
+        Q, K = ctx.estimate_grad(th, sc.views, bt.targets[0], seed, t, pairs, sc.eps)
+        ctx.step(th, m, v, t, Q, K, sc.eps, pairs, kind=api.SGD, averaging=api.AVG_COUNT, lr=sc.lr)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.theta[0], th), f"step {t}"
+    st = bt.stats()
+    assert st["tile_overflows"] > 0
+    assert (st["full_scans"] > 0) == big, st

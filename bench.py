@@ -537,9 +537,10 @@ def main_soup(args, torch, api, scenes, dev):
             l1 = float(ctx.loss(th, sc.views, tg).sum())
             rows.append({"triangles": n, "d": sc.n_params, "estimator": name, "loss_ratio": l1 / l0,
                          "ms_per_step": start.elapsed_time(stop) / args.soup_steps, "tile_px": tuning[0],
-                         "bin_capacity": tuning[1], "tile_overflows": ctx.stats()["tile_overflows"]})
+                         "bin_capacity": tuning[1], "tile_overflows": ctx.stats()["tile_overflows"],
+                         "full_scans": ctx.stats()["full_scans"]})
             progress(f"soup {n} {name}: loss ratio {l1 / l0:.4f}, {rows[-1]['ms_per_step']:.2f} ms/step, "
-                     f"tuning {tuning}, overflows {rows[-1]['tile_overflows']}")
+                     f"tuning {tuning}, overflows {rows[-1]['tile_overflows']}, full scans {rows[-1]['full_scans']}")
             del ctx
     out = {"metric": f"L2 loss after {args.soup_steps} Adam steps / initial loss (N=128 pairs/step, 512^2)",
            "config": {"workload": "soup: 1K/10K/100K-triangle soups, 12 params per triangle, unlit, "

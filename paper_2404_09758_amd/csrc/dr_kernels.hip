@@ -844,6 +844,11 @@ __device__ __forceinline__ void tile_body(const TileJob& J, TileShared<TILE, MOD
     const int cx1 = min(px0 + TILE - 1, vw.W - 1), cy1 = min(py0 + TILE - 1, vw.H - 1);   // last pixel in view
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    if constexpr (MODE == 0 || MODE == 3) {
+        // no triangle of either render touches the tile: every pixel is
+        // background in both, so the tile adds nothing (its bins are empty)
+        if ((J.counts[0][J.tile] | J.counts[NS - 1][J.tile]) == 0u) return;
+    }
     for (int j = tid; j < NS * NPIX; j += TB) (&S.key[0][0])[j] = ~0ull;
     __syncthreads();
 
@@ -1133,6 +1138,10 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
     const int cx1 = min(px0 + TILE - 1, vw.W - 1), cy1 = min(py0 + TILE - 1, vw.H - 1);   // last pixel in view
     int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    if constexpr (MODE == 0 || MODE == 3) {
+        // no fragment in either render: the tile adds nothing
+        if ((J.counts[0][J.tile] | J.counts[NS - 1][J.tile]) == 0u) return;
+    }
     for (int j = tid; j < NS * NPIX * LM; j += TB) (&S.key[0][0])[j] = ~0ull;
     if constexpr (MODE == 0) {
         for (int j = tid; j < TSIZE; j += TB) {

@@ -1202,8 +1202,7 @@ extern "C" const char* dr_last_error(const dr_ctx* c) { return c ? c->err.c_str(
 struct dr_batch {
     int device = 0;
     hipStream_t stream = nullptr;      // caller's stream
-    hipStream_t gstream = nullptr;     // capture / replay stream of the graph
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t gstream = nullptr;     // capture stream of the graph (replays go to the caller's stream)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -1246,8 +1245,6 @@ static void batch_free(dr_batch* b) {
     b->timer.destroy();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->ev_signs) (void)hipEventDestroy(b->ev_signs);
     for (hipEvent_t e : b->ev_setup)
         if (e) (void)hipEventDestroy(e);
@@ -1598,12 +1595,9 @@ extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
     }
     if (!b->exec) {
         b->args.q_zero = 1;
-        // capture on a stream of our own (the caller's may be the null
-        // stream, which cannot be captured); order it after the caller's
-        // stream with events on every replay
+        // captured on a stream of our own (the caller's may be the null
+        // stream, which cannot be captured), with nothing pending on it
         BHIPCHK(b, hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking));
-        BHIPCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
-        BHIPCHK(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
         BHIPCHK(b, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
         hipError_t e = batch_enqueue(b, b->gstream, true, false);
         hipGraph_t g = nullptr;
@@ -1613,11 +1607,8 @@ extern "C" dr_status dr_batch_step(dr_batch* b, int use_graph) {
         b->graph = g;
         BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
-    BHIPCHK(b, hipEventRecord(b->ev_in, b->stream));
-    BHIPCHK(b, hipStreamWaitEvent(b->gstream, b->ev_in, 0));
-    BHIPCHK(b, hipGraphLaunch(b->exec, b->gstream));
-    BHIPCHK(b, hipEventRecord(b->ev_out, b->gstream));
-    BHIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    // replayed on the caller's stream itself: no cross-stream waits between steps
+    BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
     return DR_OK;
 }
 

@@ -143,6 +143,15 @@ def test_paper_step_in_the_bench_launch_shape_matches_oracle():
     o.step(th_o, m_o, v_o, step, Qo2, Ko2, sc.eps, sc.n_pairs, kind=S.OPT_ADAM, averaging=S.AVG_COUNT, lr=sc.lr)
     assert np.array_equal(host(bt.theta[0]), th_o)
     assert np.array_equal(host(bt.m[0]), m_o) and np.array_equal(host(bt.v[0]), v_o)
+    # further graph replays equal plain steps at this size too
+    ctx = api.Context(sc, DEV, tuning=(16, 256, 0))
+    th, m, v = bt.theta[0].clone(), bt.m[0].clone(), bt.v[0].clone()
+    for t in range(step + 1, step + 4):
+        bt.step(use_graph=True)
+        Q, K = ctx.estimate_grad(th, sc.views, bt.targets[0], seed, t, sc.n_pairs, sc.eps)
+        ctx.step(th, m, v, t, Q, K, sc.eps, sc.n_pairs, kind=api.ADAM, averaging=api.AVG_COUNT, lr=sc.lr)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.theta[0], th) and torch.equal(bt.m[0], m) and torch.equal(bt.v[0], v), f"step {t}"
 
 
 @pytest.mark.parametrize("pairs", [2, 11])
@@ -230,3 +239,4 @@ def test_sixteen_batch_config_scenes_match_plain_and_oracle():
             assert torch.equal(bt.theta[b], th[b]), f"step {step}, scene {b}"
             assert torch.equal(bt.m[b], m[b]) and torch.equal(bt.v[b], v[b])
     assert bt.stats()["tile_overflows"] == 0
+

@@ -1534,10 +1534,10 @@ static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool 
         if ((e = hipEventRecord(b->ev_signs, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(b->astream, b->ev_signs, 0)) != hipSuccess) return e;
         for (size_t g = 1; g < G; ++g) {
-            if ((e = launch_batch_setup(b->astream, A, b->groups[g].blk0, b->groups[g].nblk)) != hipSuccess) return e;
+            if ((e = launch_batch_setup(b->astream, A, one, b->groups[g].blk0, b->groups[g].nblk)) != hipSuccess) return e;
             if ((e = hipEventRecord(b->ev_setup[g], b->astream)) != hipSuccess) return e;
         }
-        if ((e = launch_batch_setup(st, A, b->groups[0].blk0, b->groups[0].nblk)) != hipSuccess) return e;
+        if ((e = launch_batch_setup(st, A, one, b->groups[0].blk0, b->groups[0].nblk)) != hipSuccess) return e;
         for (size_t g = 0; g < G; ++g) {
             if (g > 0 && (e = hipStreamWaitEvent(st, b->ev_setup[g], 0)) != hipSuccess) return e;
             if ((e = launch_batch_tile(st, A, one, b->groups[g].w0, b->groups[g].nw)) != hipSuccess) return e;
@@ -1545,7 +1545,7 @@ static hipError_t batch_enqueue(dr_batch* b, hipStream_t st, bool descend, bool 
     } else {
         for (size_t g = 0; g < G; ++g) {
             const auto& gr = b->groups[g];
-            if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A, gr.blk0, gr.nblk); })) != hipSuccess)
+            if ((e = T.run(st, K_SETUP, [&] { return launch_batch_setup(st, A, one, gr.blk0, gr.nblk); })) != hipSuccess)
                 return e;
             if ((e = T.run(st, K_TILE, [&] { return launch_batch_tile(st, A, one, gr.w0, gr.nw); })) != hipSuccess)
                 return e;

@@ -55,20 +55,14 @@ __global__ void k_signs(unsigned long long seed, unsigned step, unsigned pair0, 
 // setup record, and its entries in the bins of the tiles it may cover.
 // fpos: the perturbed tessellated vertex positions of this (pair, sign) of a
 // subdivision surface, or null (positions are the perturbed parameters).
-__device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
-                                          const uint32_t* __restrict__ pb, float e0, float sgn, int t,
-                                          TriR* __restrict__ recR, TriS* __restrict__ recS,
-                                          unsigned* __restrict__ counts,
-                                          unsigned* __restrict__ bins, int tile_px, int cap,
-                                          unsigned* __restrict__ spn, unsigned long long* __restrict__ spill,
-                                          const float* __restrict__ fpos) {
-    int vid[3];
-    float p[9];
-    Vtx v[3];
+// The perturbed world positions of triangle t's corners (original order).
+__device__ __forceinline__ void tri_positions(const DScene& sc, const float* __restrict__ theta,
+                                              const uint32_t* __restrict__ pb, float e0, float sgn, int t,
+                                              const float* __restrict__ fpos, float* p) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        vid[k] = sc.tri[3 * (long long)t + k];
-        long long base = 3 * (long long)vid[k];
+        const int vid = sc.tri[3 * (long long)t + k];
+        long long base = 3 * (long long)vid;
         if (fpos) {
             p[3 * k + 0] = fpos[base + 0];
             p[3 * k + 1] = fpos[base + 1];
@@ -78,8 +72,18 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
             p[3 * k + 1] = pval(theta, base + 1, e0, pb, sgn);
             p[3 * k + 2] = pval(theta, base + 2, e0, pb, sgn);
         }
-        v[k] = xform(vw, p[3 * k + 0], p[3 * k + 1], p[3 * k + 2]);
     }
+}
+
+// Setup and binning of triangle t in one view from its perturbed corners p.
+__device__ __forceinline__ void setup_tri_at(const DView& vw, const float* p, int t,
+                                             TriR* __restrict__ recR, TriS* __restrict__ recS,
+                                             unsigned* __restrict__ counts,
+                                             unsigned* __restrict__ bins, int tile_px, int cap,
+                                             unsigned* __restrict__ spn, unsigned long long* __restrict__ spill) {
+    Vtx v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = xform(vw, p[3 * k + 0], p[3 * k + 1], p[3 * k + 2]);
     TriR r;
     TriS sh;
     r.flags = 0u;
@@ -186,6 +190,18 @@ __device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, con
             }
         }
     }
+}
+
+__device__ __forceinline__ void setup_tri(const DScene& sc, const DView& vw, const float* __restrict__ theta,
+                                          const uint32_t* __restrict__ pb, float e0, float sgn, int t,
+                                          TriR* __restrict__ recR, TriS* __restrict__ recS,
+                                          unsigned* __restrict__ counts,
+                                          unsigned* __restrict__ bins, int tile_px, int cap,
+                                          unsigned* __restrict__ spn, unsigned long long* __restrict__ spill,
+                                          const float* __restrict__ fpos) {
+    float p[9];
+    tri_positions(sc, theta, pb, e0, sgn, t, fpos, p);
+    setup_tri_at(vw, p, t, recR, recS, counts, bins, tile_px, cap, spn, spill);
 }
 
 __global__ void __launch_bounds__(256) k_setup_bin(SetupArgs a) {
@@ -1624,6 +1640,33 @@ __global__ void __launch_bounds__(256) k_setup_b(BatchArgs b) {
               b.spill + (I.sp_off + s) * SPILL_CAP, nullptr);
 }
 
+// Setup of a one-scene batch: a thread takes one (pair, sign, triangle)
+// and sets the triangle up in every view, so the perturbed corners (index,
+// parameter and sign reads) are formed once for all the views.  Items are
+// numbered (pair, view).
+__global__ void __launch_bounds__(256) k_setup_b1(BatchArgs b, BatchOne one) {
+    const DScene& sc = one.sc;
+    const BScene& S = b.scenes[0];
+    const long long per_sign = ((long long)sc.n_tris + 255) >> 8;
+    const long long blk = blockIdx.x;
+    const int pair = (int)(blk / (2 * per_sign));
+    const long long rem = blk - (long long)pair * 2 * per_sign;
+    const int s = (int)(rem / per_sign);
+    const int t = (int)((rem - s * per_sign) * 256 + threadIdx.x);
+    if (t >= sc.n_tris) return;
+    float p[9];
+    tri_positions(sc, S.theta, S.bits + (long long)pair * sc.words, S.eps[0], s == 0 ? 1.0f : -1.0f, t, nullptr, p);
+    for (int v = 0; v < one.n_views; ++v) {
+        const BItem& I = b.items[pair * one.n_views + v];
+        const DView& vw = one.views[v];
+        const int tiles = vw.tiles_x * vw.tiles_y;
+        setup_tri_at(vw, p, t, b.recR + I.rec_off + (long long)s * sc.n_tris,
+                     b.recS + I.rec_off + (long long)s * sc.n_tris, b.counts + I.cnt_off + (long long)s * tiles,
+                     b.bins + I.bin_off + (long long)s * tiles * I.cap, b.tile, I.cap, b.spn + 2 * (I.sp_off + s),
+                     b.spill + (I.sp_off + s) * SPILL_CAP);
+    }
+}
+
 // Raster / shade / scatter of every (scene, pair, view, tile) unit in one
 // launch: one workgroup per unit, units in the XCD-aware order of
 // xcd_tile(), items of the costliest scenes first.
@@ -1910,8 +1953,15 @@ hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, long long blk0, long long nblk) {
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, const BatchOne* one, long long blk0,
+                              long long nblk) {
     if (nblk <= 0) return hipSuccess;
+    if (one && blk0 == 0 && nblk == b.setup_blocks) {
+        // the whole setup of a one-scene batch: a thread per (pair, sign, triangle)
+        const long long blocks = (long long)b.n_pairs * 2 * (((long long)one->sc.n_tris + 255) >> 8);
+        hipLaunchKernelGGL(k_setup_b1, dim3((unsigned)blocks), dim3(256), 0, st, b, *one);
+        return hipGetLastError();
+    }
     BatchArgs a = b;
     a.unit0 = blk0;
     hipLaunchKernelGGL(k_setup_b, dim3((unsigned)nblk), dim3(256), 0, st, a);

@@ -192,7 +192,10 @@ hipError_t launch_step(hipStream_t st, const StepArgs& a);
 
 hipError_t launch_batch_signs(hipStream_t st, const BatchArgs& b);
 // setup blocks [blk0, blk0 + nblk) of the batch's setup grid
-hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, long long blk0, long long nblk);
+struct BatchOne;
+// setup blocks [blk0, blk0 + nblk); one: the batch's scene when it has one
+hipError_t launch_batch_setup(hipStream_t st, const BatchArgs& b, const BatchOne* one, long long blk0,
+                              long long nblk);
 // A one-scene batch's scene constants and views, passed to the tile launch
 // by value.
 struct BatchOne {

@@ -347,7 +347,7 @@ struct __align__(16) PTri {
     unsigned t;
     int off0;            // key index of the corner pixel
     int bw;              // box width
-    unsigned m;          // ceil(2^20 / bw)
+    unsigned m;          // ceil(2^20 / slots per row), slots of two pixels
     int pex;             // the triangle's first slot in the packed sequence
     int pad;
 };
@@ -371,19 +371,28 @@ __device__ __forceinline__ void wave_sync() {
 static_assert(sizeof(PTri) == 80, "PTri layout");
 
 // Packed raster of a batch whose triangles are all TRI_SMALL, through the
-// wave's LDS stage.  The batch's non-empty triangles are stored by rank;
-// each pass marks the slots where a triangle begins, and a lane's triangle
-// is then the number of triangles begun up to its slot (a ballot and a
-// lane-masked bit count) -- one LDS read of the staged record instead of a
-// binary search and a shuffle per field.  Edge values are exact: for a
+// wave's LDS stage.  Each triangle's clipped box is cut into slots of two
+// horizontally adjacent pixels (a row of w pixels gives ceil(w / 2) slots),
+// the batch's slots are laid end to end, and each pass gives one slot to
+// every lane: one read of the staged record, one index computation and one
+// pass marking then serve two pixels.  The non-empty triangles are stored
+// by rank; each pass marks the slots where a triangle begins, and a lane's
+// triangle is then the number of triangles begun up to its slot (a ballot
+// and a lane-masked bit count) -- one LDS read of the staged record instead
+// of a binary search and a shuffle per field.  Edge values are exact: for a
 // TRI_SMALL triangle both products of an edge function are below 2^30 in
 // magnitude at every pixel of the box, so the edge value (and its value
 // plus 1) fits in 32 bits and the wrapped 32-bit sums a dx + b dy + c equal
-// it; e > 0 || (e == 0 && top-left) is e + [top-left] > 0.
+// it, as does the second pixel's value, the first's plus a;
+// e > 0 || (e == 0 && top-left) is e + [top-left] > 0.
 template <int TILE, bool DEEP>
-__device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, unsigned t, int c, int x0, int y0,
-                                              int bw, int pex, int N, int px0, int py0, int lane,
-                                              unsigned long long* key, int L) {
+__device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, unsigned t, int x0, int y0, int bw,
+                                              int bh, int px0, int py0, int lane, unsigned long long* key, int L) {
+    const int sw = (bw + 1) >> 1;                       // slots per row
+    const int c = sw * bh;                              // slots of this lane's triangle (0: none)
+    const int P = wave_inclusive_sum(c);
+    const int N = __builtin_amdgcn_readlane(P, 63);
+    const int pex = P - c;
     unsigned long long nz = __ballot(c > 0);
     if (c > 0) {
         int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(nz >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)nz, 0u));
@@ -403,7 +412,7 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
         q.t = t;
         q.off0 = (y0 - py0) * TILE + (x0 - px0);
         q.bw = bw;
-        q.m = ((1u << 20) + (unsigned)bw - 1u) / (unsigned)bw;     // exact for bw <= 32, idx < 1024
+        q.m = ((1u << 20) + (unsigned)sw - 1u) / (unsigned)sw;     // exact for sw <= 32, idx < 1024
         q.pex = pex;
         q.pad = 0;
         st->tri[rank] = q;
@@ -425,14 +434,21 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
             PTri q = st->tri[rr];
             int idx = sl - q.pex;
             int dy = (int)(((unsigned)idx * q.m) >> 20);
-            int dx = idx - dy * q.bw;
+            int qsw = (q.bw + 1) >> 1;
+            int dx = 2 * (idx - dy * qsw);
             int e0 = (__mul24(q.a[0], dx) + __mul24(q.b[0], dy)) + q.c[0];
             int e1 = (__mul24(q.a[1], dx) + __mul24(q.b[1], dy)) + q.c[1];
             int e2 = (__mul24(q.a[2], dx) + __mul24(q.b[2], dy)) + q.c[2];
+            const float zrow = (float)(256 * dy + q.dz[1]);
             if (min(e0, min(e1, e2)) > 0) {
-                float z = (q.z0 + q.zx * (float)(256 * dx + q.dz[0])) + q.zy * (float)(256 * dy + q.dz[1]);
+                float z = (q.z0 + q.zx * (float)(256 * dx + q.dz[0])) + q.zy * zrow;
                 if (!(z > 0.0f)) z = 0.0f;
-                insert_key<DEEP>(key, q.off0 + dy * TILE + dx,
+                insert_key<DEEP>(key, q.off0 + dy * TILE + dx, ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
+            }
+            if (dx + 1 < q.bw && min(e0 + q.a[0], min(e1 + q.a[1], e2 + q.a[2])) > 0) {
+                float z = (q.z0 + q.zx * (float)(256 * (dx + 1) + q.dz[0])) + q.zy * zrow;
+                if (!(z > 0.0f)) z = 0.0f;
+                insert_key<DEEP>(key, q.off0 + dy * TILE + dx + 1,
                                  ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
             }
         }
@@ -456,25 +472,25 @@ __device__ __forceinline__ void raster_batch(const TriR* __restrict__ R, unsigne
                                              int py0, int cx1, int cy1, int lane, unsigned long long* key, int L,
                                              RasterStage* stage) {
     TriR r{};
-    int x0 = 0, y0 = 0, bw = 1, c = 0;
+    int x0 = 0, y0 = 0, bw = 1, bh = 0, c = 0;
     if ((unsigned)lane < n) {
         r = gload(&R[mine]);
         int x1, y1;
         tri_box(r, px0, py0, cx1, cy1, x0, x1, y0, y1);
         if (x0 <= x1 && y0 <= y1) {
             bw = x1 - x0 + 1;
-            c = bw * (y1 - y0 + 1);
+            bh = y1 - y0 + 1;
+            c = bw * bh;
         }
+    }
+    // Packed, never more passes than one triangle at a time: the staged
+    // form is taken whenever it applies.
+    if (stage != nullptr && __ballot(c > 0 && !(r.flags & TRI_SMALL)) == 0ull) {
+        raster_staged<TILE, DEEP>(stage, r, mine, x0, y0, bw, bh, px0, py0, lane, key, L);
+        return;
     }
     int P = wave_inclusive_sum(c);                      // prefix sums of the pixel counts
     int N = __builtin_amdgcn_readlane(P, 63);
-    // Packed, ceil(sum c / 64) passes, never takes more passes than one
-    // triangle at a time, sum ceil(c / 64): the staged form is taken
-    // whenever it applies.
-    if (stage != nullptr && __ballot(c > 0 && !(r.flags & TRI_SMALL)) == 0ull) {
-        raster_staged<TILE, DEEP>(stage, r, mine, c, x0, y0, bw, P - c, N, px0, py0, lane, key, L);
-        return;
-    }
     int T = wave_inclusive_sum((c + 63) >> 6);          // passes of the per-triangle loop
     int passes_tri = __builtin_amdgcn_readlane(T, 63);
     int passes_packed = (N + 63) >> 6;

@@ -327,6 +327,11 @@ def layered_scene(name):
                             views=1)
         sc.layers = 4
         return sc
+    if name == "dense2":       # 20480 triangles on 128^2 px: with capacity 1 the spill lists overflow
+        sc = H.sphere_scene(32, 0, res=(128, 128), shading=S.SHADING_UNLIT, tex_shapes=((64, 64, 4),), seed=7,
+                            views=1)
+        sc.layers = 2
+        return sc
     if name == "stack3":
         rng = np.random.default_rng(8)
         tex = rng.uniform(0.05, 0.95, (2, 6, 4)).astype(np.float32)
@@ -355,6 +360,33 @@ def test_layered_render_bit_exact(name, tile, cap):
         assert np.array_equal(host(uv), uv_o)
         assert np.array_equal(host(rgb), rgb_o)
         assert (id_o[..., 1] != oracle.BG_ID).sum() > 20          # some pixels see two layers
+    if cap == 1:
+        # overflowing bins read the spill lists: no tile tests every triangle
+        gs = ctx.stats()
+        assert gs["tile_overflows"] > 0 and gs["full_scans"] == 0, gs
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_layered_dense_full_scan_render_and_estimate_bit_exact(tile):
+    """The dense sphere spills more bin entries per render than a spill list
+    holds, so its overflowing tiles test every triangle of the render (the
+    deep buffer's atomic-min cascade then sees each triangle once)."""
+    sc = layered_scene("dense2")
+    o = oracle.Oracle(sc)
+    theta = sc.flat_params()
+    tg = targets_of(o, sc)
+    ctx = api.Context(sc, DEV, tuning=(tile, 1, 1))
+    ctx.set_adaptive_bins(False)
+    rgb_o, id_o, uv_o = o.render(theta, sc.views[0])
+    rgb, ids, uv = ctx.render(dev(theta), sc.views[0])
+    assert np.array_equal(host(ids).view(np.uint32), id_o)
+    assert np.array_equal(host(uv), uv_o) and np.array_equal(host(rgb), rgb_o)
+    assert (id_o[..., 1] != oracle.BG_ID).sum() > 20
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 6, 2, 1, sc.eps)
+    Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 6, 2, 1, sc.eps)
+    assert np.array_equal(host(K).view(np.uint32), Ko) and np.array_equal(host(Q), Qo)
+    gs = ctx.stats()
+    assert gs["tile_overflows"] > 0 and gs["full_scans"] > 0, gs
 
 
 @pytest.mark.parametrize("name,pairs,tuning,form", [("sphere2", 2, (16, 256, 0), "loss"),

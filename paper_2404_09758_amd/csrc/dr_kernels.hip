@@ -371,11 +371,11 @@ __device__ __forceinline__ void wave_sync() {
 static_assert(sizeof(PTri) == 80, "PTri layout");
 
 // Packed raster of a batch whose triangles are all TRI_SMALL, through the
-// wave's LDS stage.  Each triangle's clipped box is cut into slots of two
-// horizontally adjacent pixels (a row of w pixels gives ceil(w / 2) slots),
-// the batch's slots are laid end to end, and each pass gives one slot to
-// every lane: one read of the staged record, one index computation and one
-// pass marking then serve two pixels.  The non-empty triangles are stored
+// wave's LDS stage.  Each triangle's clipped box is cut into slots of
+// RASTER_SLOT horizontally adjacent pixels (a row of w pixels gives
+// ceil(w / RASTER_SLOT) slots), the batch's slots are laid end to end, and
+// each pass gives one slot to every lane: one read of the staged record, one
+// index computation and one pass marking then serve all the slot's pixels.  The non-empty triangles are stored
 // by rank; each pass marks the slots where a triangle begins, and a lane's
 // triangle is then the number of triangles begun up to its slot (a ballot
 // and a lane-masked bit count) -- one LDS read of the staged record instead
@@ -383,12 +383,17 @@ static_assert(sizeof(PTri) == 80, "PTri layout");
 // TRI_SMALL triangle both products of an edge function are below 2^30 in
 // magnitude at every pixel of the box, so the edge value (and its value
 // plus 1) fits in 32 bits and the wrapped 32-bit sums a dx + b dy + c equal
-// it, as does the second pixel's value, the first's plus a;
-// e > 0 || (e == 0 && top-left) is e + [top-left] > 0.
+// it, as do the slot's further pixels' values, each its left neighbour's
+// plus a; e > 0 || (e == 0 && top-left) is e + [top-left] > 0.
+// Slots of 4 pixels: measured on the paper-scale step against 2, 3, 6 and 8
+// (2 -> 4: tile kernel -2 % at the start of an optimisation run, -9 % after
+// 50 Adam steps, when the triangles have grown; 6 and 8 within 2 % of 4).
+#define RASTER_SLOT 4
 template <int TILE, bool DEEP>
 __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, unsigned t, int x0, int y0, int bw,
                                               int bh, int px0, int py0, int lane, unsigned long long* key, int L) {
-    const int sw = (bw + 1) >> 1;                       // slots per row
+    constexpr int SL = RASTER_SLOT;                     // pixels per slot
+    const int sw = (bw + SL - 1) / SL;                  // slots per row
     const int c = sw * bh;                              // slots of this lane's triangle (0: none)
     const int P = wave_inclusive_sum(c);
     const int N = __builtin_amdgcn_readlane(P, 63);
@@ -434,22 +439,23 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
             PTri q = st->tri[rr];
             int idx = sl - q.pex;
             int dy = (int)(((unsigned)idx * q.m) >> 20);
-            int qsw = (q.bw + 1) >> 1;
-            int dx = 2 * (idx - dy * qsw);
+            int qsw = (q.bw + SL - 1) / SL;
+            int dx = SL * (idx - dy * qsw);
             int e0 = (__mul24(q.a[0], dx) + __mul24(q.b[0], dy)) + q.c[0];
             int e1 = (__mul24(q.a[1], dx) + __mul24(q.b[1], dy)) + q.c[1];
             int e2 = (__mul24(q.a[2], dx) + __mul24(q.b[2], dy)) + q.c[2];
             const float zrow = (float)(256 * dy + q.dz[1]);
-            if (min(e0, min(e1, e2)) > 0) {
-                float z = (q.z0 + q.zx * (float)(256 * dx + q.dz[0])) + q.zy * zrow;
-                if (!(z > 0.0f)) z = 0.0f;
-                insert_key<DEEP>(key, q.off0 + dy * TILE + dx, ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
-            }
-            if (dx + 1 < q.bw && min(e0 + q.a[0], min(e1 + q.a[1], e2 + q.a[2])) > 0) {
-                float z = (q.z0 + q.zx * (float)(256 * (dx + 1) + q.dz[0])) + q.zy * zrow;
-                if (!(z > 0.0f)) z = 0.0f;
-                insert_key<DEEP>(key, q.off0 + dy * TILE + dx + 1,
-                                 ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                if ((k == 0 || dx + k < q.bw) && min(e0, min(e1, e2)) > 0) {
+                    float z = (q.z0 + q.zx * (float)(256 * (dx + k) + q.dz[0])) + q.zy * zrow;
+                    if (!(z > 0.0f)) z = 0.0f;
+                    insert_key<DEEP>(key, q.off0 + dy * TILE + dx + k,
+                                     ((unsigned long long)__float_as_uint(z) << 32) | q.t, L);
+                }
+                e0 += q.a[0];
+                e1 += q.a[1];
+                e2 += q.a[2];
             }
         }
         wave_sync();

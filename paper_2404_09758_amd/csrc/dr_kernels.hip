@@ -1135,7 +1135,11 @@ struct DeepShared {
     static constexpr int NS = (MODE == 0 || MODE == 3) ? 2 : 1;
     static constexpr int LOG2T = MODE == 0 ? TileCfg<TILE>::LOG2T : 1;
     unsigned long long key[NS][NPIX * DRD_MAX_LAYERS];
-    GroupTable<LOG2T> table;
+    // the raster's per-wave stages, then (estimate) the group table
+    union {
+        RasterStage stage[TB / 64 > 0 ? TB / 64 : 1];
+        GroupTable<LOG2T> table;
+    } u;
     double red[MODE == 2 ? TB : 1];
     long long qred[MODE == 3 ? TB : 1];
 };
@@ -1181,12 +1185,6 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         if ((J.counts[0][J.tile] | J.counts[NS - 1][J.tile]) == 0u) return;
     }
     for (int j = tid; j < NS * NPIX * LM; j += TB) (&S.key[0][0])[j] = ~0ull;
-    if constexpr (MODE == 0) {
-        for (int j = tid; j < TSIZE; j += TB) {
-            S.table.key[j] = HASH_EMPTY;
-            S.table.sum[j] = 0ull;
-        }
-    }
     __syncthreads();
 
 #pragma unroll
@@ -1196,12 +1194,19 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         const TriR* __restrict__ R = J.recR[s];
         raster_render<TILE, true>(R, J.bins[s] + (long long)J.tile * J.cap, cnt, (unsigned)J.cap, J.spn[s],
                                   J.spill[s], sc.n_tris, J.tile, wave, NW, lane, px0, py0, cx1, cy1, S.key[s], L,
-                                  nullptr, J.stats, wave == 0);
+                                  &S.u.stage[wave], J.stats, wave == 0);
     }
     __syncthreads();
     if (tid == 0) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) release_bin(J.counts[s], J.tile, (unsigned)J.cap, J.spn[s]);
+    }
+    if constexpr (MODE == 0) {
+        // the stages are done with: the group table takes their place
+        for (int j = tid; j < TSIZE; j += TB) {
+            S.u.table.key[j] = HASH_EMPTY;
+            S.u.table.sum[j] = 0ull;
+        }
     }
 
     int local = tid;
@@ -1294,6 +1299,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
         return;
     }
     if constexpr (MODE == 0) {
+        __syncthreads();                             // the group table is cleared
         bool act = inpix && any && J.any_act;
         if (act) {
             int flag;
@@ -1323,7 +1329,7 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, (unsigned)v1[k], q, 1u);
+                        if (!dup[k]) table_add<LOG2T>(S.u.table, J.Rp, J.K, (unsigned)v1[k], q, 1u);
                 }
                 if (J.any_act && sc.n_cls > 0) {
                     Attr a1 = frag_attr(sc, (s1 ? J.recR[1] : J.recR[0])[id1], (s1 ? J.recS[1] : J.recS[0])[id1],
@@ -1355,18 +1361,18 @@ __device__ __forceinline__ void tile_body_deep(const TileJob& J, DeepShared<TILE
                         }
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
-                            if (!dup[k]) table_add<LOG2T>(S.table, J.Rp, J.K, gs[k], q, 1u);
+                            if (!dup[k]) table_add<LOG2T>(S.u.table, J.Rp, J.K, gs[k], q, 1u);
                     }
                 }
             }
         }
         __syncthreads();
         for (int j = tid; j < TSIZE; j += TB) {
-            unsigned g = S.table.key[j];
+            unsigned g = S.u.table.key[j];
             if (g != HASH_EMPTY) {
                 long long q;
                 unsigned c;
-                unpack_sc(S.table.sum[j], q, c);
+                unpack_sc(S.u.table.sum[j], q, c);
                 global_add(J.Rp, J.K, (long long)g, q, c);
             }
         }

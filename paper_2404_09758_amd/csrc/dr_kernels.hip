@@ -463,8 +463,9 @@ __device__ __forceinline__ void raster_staged(RasterStage* st, const TriR& r, un
 }
 
 // Raster of up to 64 triangles held one per lane (mine: the triangle
-// index, valid for lanes below n).  Lane-packed when that takes fewer
-// passes: the triangles' clipped bounding boxes are laid end to end (a
+// index, valid for lanes below n).  A batch of TRI_SMALL triangles goes
+// through the wave's LDS stage (raster_staged) whenever there is one.
+// Otherwise, lane-packed when that takes fewer passes: the triangles' clipped bounding boxes are laid end to end (a
 // prefix sum of their pixel counts) and each pass gives one pixel of that
 // sequence to every lane, which finds its triangle by binary search over
 // the prefix sums and reads the triangle's data from its lane.  For small
@@ -597,8 +598,9 @@ __device__ __forceinline__ void raster_bin(const unsigned* __restrict__ list, un
     }
 }
 
-// A tile whose bin overflowed: every valid triangle of the render whose
-// pixel box meets the tile, found 64 at a time (one record's flags and box
+// A tile whose bin overflowed while its render's spill list was full (or
+// absent): every valid triangle of the render whose pixel box meets the
+// tile, found 64 at a time (one record's flags and box
 // per lane), packed to the low lanes and rasterised as one batch.  The cost
 // is one coalesced pass over the render's records per overflowing tile,
 // not one dependent record read per triangle.

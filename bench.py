@@ -393,7 +393,8 @@ def main():
     traffic = measured_traffic(kernel) if args.config == "paper" else None
     achieved = alg_bytes_launch / (tile_avg_ms * 1e-3) / 1e9
     out = {
-        "metric": METRIC,
+        # the headline metric names the paper-scale workload; other workloads say which they are
+        "metric": METRIC if args.config == "paper" else f"optimisation steps/s, {args.config} workload",
         "value": 1e3 / r["ms_per_step"],
         "unit": "steps/s",
         "n_gpus": 1,
@@ -475,7 +476,8 @@ def main_batch64(args, torch, api, autotune, batch, scenes, dev):
     alg = BYTES_PER_PIXEL_ESTIMATE * px / (tm["tile_launches"] / args.steps)
     achieved = alg / (tile_avg_ms * 1e-3) / 1e9
     out = {
-        "metric": METRIC, "value": 1e3 / g["ms_per_step"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "metric": "optimisation steps/s of 64 uneven scenes (graph-captured batched step vs 64 sequential plain steps)",
+        "value": 1e3 / g["ms_per_step"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch64: {n} scenes, F in [{min(s.n_tris for s in scs)}, "

@@ -154,6 +154,35 @@ def test_paper_step_in_the_bench_launch_shape_matches_oracle():
         assert torch.equal(bt.theta[0], th) and torch.equal(bt.m[0], m) and torch.equal(bt.v[0], v), f"step {t}"
 
 
+def test_mid_step_in_the_bench_launch_shape_matches_oracle():
+    """The mid workload at full size (512^2, 20 480 triangles, Lambert,
+    8 ring views x 16 pairs, Adam lr 1e-3) in the bench's launch shape (one
+    batch scene, tile 16, capacity 256; more than 8 pairs take the separate
+    fold and Adam kernels): the Q and K of one estimate equal the oracle's
+    over all 128 items, and the Adam step that follows equals the oracle's
+    step, bit for bit (Sec. 5)."""
+    sc = S.make_mid()
+    o = oracle.Oracle(sc)
+    tg = [o.render(sc.flat_params(True), v)[0] for v in sc.views]
+    seed, step = sc.seed, 1
+    print(f"[mid] oracle estimate of {sc.n_pairs} pairs x {len(sc.views)} views", flush=True)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, seed, step, sc.n_pairs, sc.eps)
+    bt = batch.Batch([sc], sc.n_pairs, DEV, tile_px=16, seed=seed, first_step=step, bin_capacities=[256],
+                     targets=[[torch.tensor(t, device=DEV) for t in tg]])
+    bt.estimate()
+    assert np.array_equal(host(bt.K[0]).view(np.uint32), Ko)
+    assert np.array_equal(host(bt.Q[0]), Qo)
+    bt.Q[0].zero_()
+    bt.K[0].zero_()
+    bt.step(use_graph=True)
+    th_o, m_o, v_o = theta.copy(), np.zeros(o.d, np.float32), np.zeros(o.d, np.float32)
+    o.step(th_o, m_o, v_o, step, Qo.copy(), Ko.copy(), sc.eps, sc.n_pairs, kind=S.OPT_ADAM, averaging=S.AVG_COUNT,
+           lr=sc.lr)
+    assert np.array_equal(host(bt.theta[0]), th_o)
+    assert np.array_equal(host(bt.m[0]), m_o) and np.array_equal(host(bt.v[0]), v_o)
+
+
 @pytest.mark.parametrize("pairs", [2, 11])
 def test_batch_step_after_estimate_matches_plain(pairs):
     """A descent after an estimate that left sums in Q: the fused fold and

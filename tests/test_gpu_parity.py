@@ -230,6 +230,34 @@ def test_views_of_different_sizes_in_one_call():
         assert np.array_equal(host(Q), Qo) and np.array_equal(host(K).view(np.uint32), Ko)
 
 
+@pytest.mark.parametrize("dist", [0.6, 1.08])
+def test_cameras_inside_and_at_the_surface_bit_exact(dist):
+    """Cameras inside the unit sphere and just outside its surface: some
+    triangles have corners behind the near plane (culled whole, by both
+    sides alike) and others span far more than a tile; render and estimate
+    equal the oracle's bit for bit at two launch shapes."""
+    sc = scene_by_name("lambert")
+    sc.views = [S.look_at_view(96, 80, 30.0, 10.0, dist=dist), S.look_at_view(64, 64, 200.0, -30.0, dist=dist)]
+    v = sc.views[0]
+    P = np.concatenate([sc.pos.astype(np.float64), np.ones((len(sc.pos), 1))], 1) @ v.view_proj.astype(np.float64).T
+    behind = P[:, 3] < v.near
+    assert (behind[sc.tri].any(1) & ~behind[sc.tri].all(1)).sum() > 0      # triangles straddle the near plane
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 12, 3, 2, sc.eps)
+    for tuning in [(16, 256, 1), (8, 4, 0)]:
+        ctx = api.Context(sc, DEV, tuning=tuning)
+        ctx.set_adaptive_bins(False)
+        for view in sc.views:
+            rgb_o, id_o, uv_o = o.render(theta, view)
+            rgb, ids, uv = ctx.render(dev(theta), view)
+            assert np.array_equal(host(ids).view(np.uint32), id_o)
+            assert np.array_equal(host(rgb), rgb_o) and np.array_equal(host(uv), uv_o)
+        Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 12, 3, 2, sc.eps)
+        assert np.array_equal(host(K).view(np.uint32), Ko) and np.array_equal(host(Q), Qo)
+
+
 def test_invalid_arguments_raise():
     sc = scene_by_name("tiny")
     ctx = api.Context(sc, DEV)

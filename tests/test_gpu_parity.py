@@ -258,6 +258,37 @@ def test_cameras_inside_and_at_the_surface_bit_exact(dist):
         assert np.array_equal(host(K).view(np.uint32), Ko) and np.array_equal(host(Q), Qo)
 
 
+@pytest.mark.parametrize("lo,hi", [(-0.9, 0.9), (-1.0, 1.0)])
+def test_widest_view_bit_exact(lo, hi):
+    """The widest view the ABI accepts (16384 px; Sec. 4.4's raster at its
+    largest coordinates): snapped x reaches 2^22 subpixels, the limit of a
+    valid corner -- a grid reaching x = +-1 puts corners exactly on it.
+    Render and estimate equal the oracle's bit for bit."""
+    g = H.grid_scene(8, 0.3, 5, lo=lo, hi=hi)
+    rng = np.random.default_rng(21)
+    uv = np.stack([(g.pos[:, 0] + 1.0) * 0.5, (1.0 - g.pos[:, 1]) * 0.5], 1).astype(np.float32)
+    tex = [rng.uniform(0.05, 0.95, (8, 32, 3)).astype(np.float32)]
+    ttex = [rng.uniform(0.05, 0.95, (8, 32, 3)).astype(np.float32)]
+    tpos = (g.pos + rng.normal(0.0, 0.002, g.pos.shape)).astype(np.float32)
+    sc = S.Scene("wide", g.tri, uv[g.tri], g.pos, tex, tpos, ttex, [H.ndc_view(16384, 3), H.ndc_view(16, 1)],
+                 shading=S.SHADING_UNLIT, eps=[1e-3, 1.0 / 255.0], lr=[1e-3, 1.0 / 255.0], n_pairs=1)
+    o = oracle.Oracle(sc)
+    tg = targets_of(o, sc)
+    theta = sc.flat_params()
+    Qo, Ko, _, _ = o.estimate(theta, sc.views, tg, 3, 1, 2, sc.eps)
+    assert Ko.sum() > 0
+    for tuning in [(16, 256, 1), (32, 8, 0)]:
+        ctx = api.Context(sc, DEV, tuning=tuning)
+        ctx.set_adaptive_bins(False)
+        for view in sc.views:
+            rgb_o, id_o, uv_o = o.render(theta, view)
+            rgb, ids, uvg = ctx.render(dev(theta), view)
+            assert np.array_equal(host(ids).view(np.uint32), id_o)
+            assert np.array_equal(host(rgb), rgb_o) and np.array_equal(host(uvg), uv_o)
+        Q, K = ctx.estimate_grad(dev(theta), sc.views, [dev(t) for t in tg], 3, 1, 2, sc.eps)
+        assert np.array_equal(host(K).view(np.uint32), Ko) and np.array_equal(host(Q), Qo)
+
+
 def test_invalid_arguments_raise():
     sc = scene_by_name("tiny")
     ctx = api.Context(sc, DEV)
